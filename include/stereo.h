@@ -1,0 +1,184 @@
+/*
+ * stereo.h -- C ABI of the MI355X (gfx950) road-stereo library.
+ *
+ * The library implements the dense road stereo method of Fan et al.,
+ * "Real-Time Dense Stereo Embedded in A UAV for Road Inspection"
+ * (arXiv 1904.06017):
+ *   perspective transformation of the target image   (Sec. 3.1, Eq. 4)
+ *   NCC matching costs for two cost volumes          (Sec. 3.2.1, Eq. 8)
+ *   bilateral cost aggregation                       (Sec. 3.2.1, Eqs. 10-11)
+ *   winner-take-all, left-right check, sub-pixel     (Sec. 3.2.2, Eqs. 12-13)
+ *   roll-angle fit and disparity transformation      (Sec. 3.3, Eqs. 14-29)
+ * plus a differentiable soft-argmin head with its adjoint and a batched
+ * persistent launch over many pairs.
+ *
+ * Conventions (apply to every call unless stated otherwise)
+ *   - Every call returns a stereo_status; nothing throws across the ABI.
+ *     stereo_last_error() returns a thread-local message for the last failure.
+ *   - The caller owns every buffer.  Device buffers are plain device pointers
+ *     (e.g. from hipMalloc or a framework allocator).  Inputs are const and
+ *     never written; outputs are fully overwritten.
+ *   - Images are row-major [H][W] with an element pitch >= W.  Disparity maps
+ *     and other per-pixel outputs are dense [H][W] (pitch W).  Cost volumes
+ *     are dense FP32 [D][H][W], slice d at offset d*H*W.
+ *   - Enqueue calls are asynchronous on the given stream, allocate nothing and
+ *     never synchronise the host, so they can be captured into a hipGraph.
+ *     Device faults surface at the next synchronisation of that stream.
+ *   - A plan is immutable host state; one plan may be used from several
+ *     streams at once provided each stream uses its own workspace.
+ *   - Coordinates: u (column) grows to the right, v (row) downwards, origin at
+ *     the top-left pixel.  Disparity levels d' = 0..D-1 are searched after the
+ *     perspective transformation; the residual disparity is d' - delta_p.
+ */
+#ifndef MI355X_ROAD_STEREO_H
+#define MI355X_ROAD_STEREO_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STEREO_OK = 0,
+  STEREO_ERR_INVALID_ARGUMENT = 1,   /* null pointer, bad size, bad parameter */
+  STEREO_ERR_UNSUPPORTED = 2,        /* radius / D above the compiled limits  */
+  STEREO_ERR_WORKSPACE_TOO_SMALL = 3,
+  STEREO_ERR_HIP = 4,                /* a HIP runtime call or launch failed   */
+  STEREO_ERR_NOT_CONVERGED = 5       /* road fit hit max_iter; outputs written */
+} stereo_status;
+
+typedef enum { STEREO_U8 = 0, STEREO_F32 = 1 } stereo_dtype;
+
+/* Compiled limits. */
+#define STEREO_MAX_NCC_RADIUS 8      /* r: NCC block (2r+1)^2                */
+#define STEREO_MIN_BIL_RADIUS 1
+#define STEREO_MAX_BIL_RADIUS 8      /* R: bilateral window (2R+1)^2          */
+#define STEREO_MAX_DISP 256          /* D                                     */
+
+typedef struct {
+  int32_t width, height;          /* W, H >= 1                               */
+  int64_t pitch_ref, pitch_tar;   /* elements per image row, >= width        */
+  stereo_dtype dtype;             /* pixel type of ref and tar               */
+  int32_t num_disp;               /* D >= 3 disparity levels                 */
+  float delta_p;                  /* delta_p of Sec. 3.1 (0 without warp)    */
+  int32_t perspective;            /* 1: warp the target by the road plane    */
+  double plane[3];                /* d_road(u,v) = c0 + c1 u + c2 v, pixels  */
+  int32_t ncc_radius;             /* r, 1..STEREO_MAX_NCC_RADIUS             */
+  int32_t bil_radius;             /* R, 1..STEREO_MAX_BIL_RADIUS             */
+  float sigma_s, sigma_r;         /* sigma_0, sigma_1 of Eq. (10), > 0       */
+  float lr_delta;                 /* delta_r of Eq. (12) (paper: 1)          */
+  int32_t lr_check;               /* 1: build the target volume and check    */
+  float softargmin_T;             /* temperature of the soft-argmin head > 0 */
+} stereo_params;
+
+typedef struct stereo_plan_s* stereo_plan_t;
+
+/* Result of the road fit (Sec. 3.3); written to device memory. */
+typedef struct {
+  double psi;        /* roll angle, (-pi/2, pi/2]                            */
+  double alpha0;     /* Eq. (21) at psi                                      */
+  double alpha1;
+  double e_min;      /* Eq. (23) at psi (unnormalised)                       */
+  double plane[3];   /* (alpha0, -alpha1 sin psi, alpha1 cos psi)            */
+  double n_points;   /* pixels used by the fit                               */
+  int32_t iters;
+  int32_t converged; /* 1 converged, 0 hit max_iter                          */
+  int32_t flat;      /* 1 if |alpha1(psi0)| < 1e-6: psi returned unchanged    */
+  int32_t pad_;
+} stereo_road_fit;
+
+/* ---- status ------------------------------------------------------------ */
+const char* stereo_status_string(stereo_status s);
+/* Message for the last failing call on this thread ("" if none). */
+const char* stereo_last_error(void);
+/* Library version string. */
+const char* stereo_version(void);
+
+/* ---- plans (host only; no device calls) ---------------------------------
+ * stereo_plan_create validates *params (copied) and returns a plan, or
+ * INVALID_ARGUMENT / UNSUPPORTED.  stereo_plan_workspace_bytes reports the
+ * device workspace every enqueue call of this plan needs (one size for all).
+ * stereo_plan_destroy accepts NULL. */
+stereo_status stereo_plan_create(const stereo_params* params, stereo_plan_t* out);
+stereo_status stereo_plan_destroy(stereo_plan_t plan);
+stereo_status stereo_plan_workspace_bytes(stereo_plan_t plan, size_t* bytes);
+stereo_status stereo_plan_get_params(stereo_plan_t plan, stereo_params* out);
+
+/* ---- perspective transformation, Sec. 3.1, Eq. (4) ----------------------
+ * tar: [H][pitch_tar] of params.dtype.  tar_w: [H][W] FP32.
+ * tar_w(x,v) = lerp of row v at X = x + delta_p - d_road(x + delta_p, v),
+ * X clamped to [0, W-1].  Without perspective, tar_w = tar (converted). */
+stereo_status stereo_warp(stereo_plan_t plan, const void* tar, float* tar_w,
+                          hipStream_t stream);
+
+/* ---- NCC cost volumes, Sec. 3.2.1, Eq. (8) ------------------------------
+ * ref: [H][pitch_ref] of params.dtype; tar_w: [H][W] FP32 (stereo_warp).
+ * cost_R[d][v][u] = 1 - NCC(ref block at (u,v), tar_w block at (u-d,v));
+ * cost_T[d][v][x] = 1 - NCC(ref block at (x+d,v), tar_w block at (x,v))
+ * (nullable).  Blocks are (2r+1)^2 with clamped reads; population
+ * statistics; a block with variance < 1e-6 has cost 1. */
+stereo_status stereo_cost_volume(stereo_plan_t plan, const void* ref,
+                                 const float* tar_w, float* cost_R,
+                                 float* cost_T, void* ws, size_t ws_bytes,
+                                 hipStream_t stream);
+
+/* ---- bilateral aggregation, Eqs. (10)-(11) ------------------------------
+ * cost_out[d][p] = sum_q w(p,q) cost_in[d][q] / sum_q w(p,q) over the
+ * (2R+1)^2 window truncated to the image, w = exp(-|p-q|^2/sigma_s^2
+ * - (G(p)-G(q))^2/sigma_r^2).  guide: [H][guide_pitch] of guide_dtype (the
+ * reference image for the reference volume, tar_w for the target volume). */
+stereo_status stereo_bilateral_aggregate(stereo_plan_t plan, const void* guide,
+                                         stereo_dtype guide_dtype,
+                                         int64_t guide_pitch,
+                                         const float* cost_in, float* cost_out,
+                                         hipStream_t stream);
+
+/* ---- winner-take-all + sub-pixel, Sec. 3.2.2, Eq. (13) ------------------
+ * dint[p] = first argmin_d agg[d][p] (int16).  dsub (nullable, FP32):
+ * dint + (E(d-1) - E(d+1)) / (2E(d-1) + 2E(d+1) - 4E(d)) where 0 < d < D-1
+ * and the denominator is > 0, else dint. */
+stereo_status stereo_wta_subpixel(stereo_plan_t plan, const float* agg,
+                                  int16_t* dint, float* dsub,
+                                  hipStream_t stream);
+
+/* ---- left-right check + shift back, Eq. (12), Sec. 3.2.2 ----------------
+ * valid[p] = (u - dR >= 0) && (dR - dT(u - dR, v))^2 <= lr_delta (uint8 0/1).
+ * disp[p] = dsub - delta_p + d_road(u - dsub + delta_p, v) where valid, NaN
+ * elsewhere (dsub itself when perspective = 0).  dint_T may be NULL only
+ * when params.lr_check = 0 (then valid = (u - dR >= 0)). */
+stereo_status stereo_lr_check(stereo_plan_t plan, const int16_t* dint_R,
+                              const int16_t* dint_T, const float* dsub_R,
+                              uint8_t* valid, float* disp, hipStream_t stream);
+
+/* ---- whole plain forward (warp .. shift back), fused where it pays ------
+ * Same results as stereo_warp, stereo_cost_volume, stereo_bilateral_aggregate
+ * (twice), stereo_wta_subpixel and stereo_lr_check in sequence, without
+ * materialising the aggregated volumes.  dint_T and dsub may be NULL. */
+stereo_status stereo_match(stereo_plan_t plan, const void* ref, const void* tar,
+                           int16_t* dint_R, int16_t* dint_T, float* dsub,
+                           uint8_t* valid, float* disp, void* ws,
+                           size_t ws_bytes, hipStream_t stream);
+
+/* ---- road fit + disparity transformation, Sec. 3.3, Eqs. (14)-(29) ------
+ * disp: [H][W] FP32 (NaN = invalid); mask: [H][W] uint8 (nullable: all).
+ * Fits the roll psi by gradient descent (Eq. 25) with the adaptive rate of
+ * Eq. (28) from psi_init, on the energy normalised by n*max(W,H)^2*a1(psi0)^2;
+ * stops when |dpsi| < delta_psi or after max_iter steps.  Writes *fit_dev
+ * (device memory) and disp_t = disp - a0 + a1 (u sin psi - v cos psi)
+ * + delta_t (NaN stays NaN).  Returns OK even when the fit did not converge;
+ * read fit_dev->converged.  No host synchronisation. */
+stereo_status stereo_road_transform(stereo_plan_t plan, const float* disp,
+                                    const uint8_t* mask, double psi_init,
+                                    double lambda0, double delta_psi,
+                                    int32_t max_iter, float delta_t,
+                                    stereo_road_fit* fit_dev, float* disp_t,
+                                    void* ws, size_t ws_bytes,
+                                    hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MI355X_ROAD_STEREO_H */

@@ -17,7 +17,9 @@ Readings where the paper is silent (also in the design notes):
     sensible first step (for a roll error dpsi the raw energy grows like
     n a1^2 var(x) dpsi^2).  When |a1(psi0)| < 1e-6 the scale uses a1 = 1 and
     the fit returns psi0 unchanged (no slope, no roll information);
-  * safeguard: a step is halved while it raises the energy or exceeds pi/4;
+  * safeguard: a step is halved while it raises the energy (by more than a
+    relative 1e-9, the rounding level of Eq. (23) evaluated in FP64 for maps
+    whose plane explains most of the variance) or exceeds pi/4;
     a non-positive or non-finite rate from Eq. (28) restarts at lambda0;
   * psi is wrapped into (-pi/2, pi/2] (E_min has period pi);
   * the iteration stops when |psi_k+1 - psi_k| < delta_psi, when the gradient
@@ -103,6 +105,9 @@ def _wrap(psi):
 def fit_roll(u, v, d, width, height, psi0=0.0, lambda0=LAMBDA0,
              delta_psi=DELTA_PSI, max_iter=100):
     """Roll angle by Eq. (25) with the adaptive rate of Eq. (28)."""
+    if len(d) < 3:          # too few points to fit a line: nothing to estimate
+        a0 = float(np.mean(d)) if len(d) else 0.0
+        return RoadFit(psi0, a0, 0.0, 0.0, 0, True, True)
     a_init = alpha(u, v, d, psi0)
     s = float(max(width, height))
     flat = abs(a_init[1]) < 1e-6
@@ -126,7 +131,7 @@ def fit_roll(u, v, d, width, height, psi0=0.0, lambda0=LAMBDA0,
     for it in range(1, max_iter + 1):
         step = -lam * g
         for _ in range(64):
-            if abs(step) <= math.pi / 4.0 and En(_wrap(psi + step)) <= E * (1.0 + 1e-12):
+            if abs(step) <= math.pi / 4.0 and En(_wrap(psi + step)) <= E * (1.0 + 1e-9):
                 break
             lam *= 0.5
             step = -lam * g

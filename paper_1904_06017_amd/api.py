@@ -1,0 +1,220 @@
+"""Python binding of the C ABI (argument marshalling only).
+
+Torch tensors provide device memory and the current HIP stream; every step
+runs in the library's HIP kernels.  Function names follow include/stereo.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import RoadFit, StereoParams, check
+
+DELTA_PSI = math.pi / 1.8e6
+LAMBDA0 = 10.0
+
+
+def make_params(width, height, num_disp, *, dtype="u8", delta_p=0.0, perspective=True,
+                plane=(0.0, 0.0, 0.0), ncc_radius=3, bil_radius=5, sigma_s=4.0,
+                sigma_r=12.0, lr_delta=1.0, lr_check=True, softargmin_T=0.1,
+                pitch_ref=None, pitch_tar=None) -> StereoParams:
+    p = StereoParams()
+    p.width, p.height = int(width), int(height)
+    p.pitch_ref = int(pitch_ref if pitch_ref is not None else width)
+    p.pitch_tar = int(pitch_tar if pitch_tar is not None else width)
+    p.dtype = _lib.U8 if dtype in ("u8", "uint8", torch.uint8) else _lib.F32
+    p.num_disp = int(num_disp)
+    p.delta_p = float(delta_p if perspective else 0.0)
+    p.perspective = 1 if perspective else 0
+    for i in range(3):
+        p.plane[i] = float(plane[i])
+    p.ncc_radius, p.bil_radius = int(ncc_radius), int(bil_radius)
+    p.sigma_s, p.sigma_r = float(sigma_s), float(sigma_r)
+    p.lr_delta = float(lr_delta)
+    p.lr_check = 1 if lr_check else 0
+    p.softargmin_T = float(softargmin_T)
+    return p
+
+
+def params_from_workload(w, **override) -> StereoParams:
+    kw = dict(dtype=w.dtype, delta_p=w.delta_p, perspective=w.perspective, plane=w.plane,
+              ncc_radius=w.ncc_radius, bil_radius=w.bil_radius, sigma_s=w.sigma_s,
+              sigma_r=w.sigma_r, lr_delta=w.lr_delta, lr_check=w.lr_check,
+              softargmin_T=w.softargmin_T)
+    kw.update(override)
+    return make_params(w.width, w.height, w.num_disp, **kw)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _p(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Plan:
+    """An immutable host plan plus a device workspace owned by this object."""
+
+    def __init__(self, params: StereoParams):
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        check(lib.stereo_plan_create(ctypes.byref(params), ctypes.byref(h)))
+        self._h = h
+        self.params = params
+        n = ctypes.c_size_t()
+        check(lib.stereo_plan_workspace_bytes(h, ctypes.byref(n)))
+        self.workspace_bytes = int(n.value)
+        self._ws = None
+
+    @classmethod
+    def from_workload(cls, w, **override):
+        return cls(params_from_workload(w, **override))
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def W(self):
+        return self.params.width
+
+    @property
+    def H(self):
+        return self.params.height
+
+    @property
+    def D(self):
+        return self.params.num_disp
+
+    @property
+    def img_dtype(self):
+        return torch.uint8 if self.params.dtype == _lib.U8 else torch.float32
+
+    def workspace(self, device="cuda"):
+        if self._ws is None or self._ws.device != torch.device(device):
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+        return self._ws
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and self._h.value:
+                _lib.load().stereo_plan_destroy(self._h)
+                self._h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+
+def warp(plan: Plan, tar):
+    _need(tar, plan.img_dtype, (plan.H, plan.W), "tar")
+    out = torch.empty((plan.H, plan.W), dtype=torch.float32, device=tar.device)
+    check(_lib.load().stereo_warp(plan.handle, _p(tar), _p(out), _stream()))
+    return out
+
+
+def cost_volume(plan: Plan, ref, tar_w, want_target=True):
+    _need(ref, plan.img_dtype, (plan.H, plan.W), "ref")
+    _need(tar_w, torch.float32, (plan.H, plan.W), "tar_w")
+    shape = (plan.D, plan.H, plan.W)
+    cR = torch.empty(shape, dtype=torch.float32, device=ref.device)
+    cT = torch.empty(shape, dtype=torch.float32, device=ref.device) if want_target else None
+    ws = plan.workspace(ref.device)
+    check(_lib.load().stereo_cost_volume(plan.handle, _p(ref), _p(tar_w), _p(cR), _p(cT),
+                                         _p(ws), plan.workspace_bytes, _stream()))
+    return cR, cT
+
+
+def bilateral_aggregate(plan: Plan, guide, cost):
+    if guide.dtype not in (torch.uint8, torch.float32):
+        raise ValueError("guide must be uint8 or float32")
+    _need(guide, guide.dtype, (plan.H, plan.W), "guide")
+    _need(cost, torch.float32, (plan.D, plan.H, plan.W), "cost")
+    out = torch.empty_like(cost)
+    gdt = _lib.U8 if guide.dtype == torch.uint8 else _lib.F32
+    check(_lib.load().stereo_bilateral_aggregate(plan.handle, _p(guide), gdt, plan.W,
+                                                 _p(cost), _p(out), _stream()))
+    return out
+
+
+def wta_subpixel(plan: Plan, agg):
+    _need(agg, torch.float32, (plan.D, plan.H, plan.W), "agg")
+    dint = torch.empty((plan.H, plan.W), dtype=torch.int16, device=agg.device)
+    dsub = torch.empty((plan.H, plan.W), dtype=torch.float32, device=agg.device)
+    check(_lib.load().stereo_wta_subpixel(plan.handle, _p(agg), _p(dint), _p(dsub), _stream()))
+    return dint, dsub
+
+
+def lr_check(plan: Plan, dint_R, dint_T, dsub_R):
+    _need(dint_R, torch.int16, (plan.H, plan.W), "dint_R")
+    if dint_T is not None:
+        _need(dint_T, torch.int16, (plan.H, plan.W), "dint_T")
+    if dsub_R is not None:
+        _need(dsub_R, torch.float32, (plan.H, plan.W), "dsub_R")
+    valid = torch.empty((plan.H, plan.W), dtype=torch.uint8, device=dint_R.device)
+    disp = torch.empty((plan.H, plan.W), dtype=torch.float32, device=dint_R.device)
+    check(_lib.load().stereo_lr_check(plan.handle, _p(dint_R), _p(dint_T), _p(dsub_R),
+                                      _p(valid), _p(disp), _stream()))
+    return valid, disp
+
+
+def match(plan: Plan, ref, tar, want_target=False, out=None):
+    """Whole plain forward; returns dint_R, dsub, valid, disp (and dint_T)."""
+    _need(ref, plan.img_dtype, (plan.H, plan.W), "ref")
+    _need(tar, plan.img_dtype, (plan.H, plan.W), "tar")
+    dev = ref.device
+    if out is None:
+        out = dict(
+            dint_R=torch.empty((plan.H, plan.W), dtype=torch.int16, device=dev),
+            dsub=torch.empty((plan.H, plan.W), dtype=torch.float32, device=dev),
+            valid=torch.empty((plan.H, plan.W), dtype=torch.uint8, device=dev),
+            disp=torch.empty((plan.H, plan.W), dtype=torch.float32, device=dev))
+        if want_target:
+            out["dint_T"] = torch.empty((plan.H, plan.W), dtype=torch.int16, device=dev)
+    ws = plan.workspace(dev)
+    check(_lib.load().stereo_match(plan.handle, _p(ref), _p(tar), _p(out["dint_R"]),
+                                   _p(out.get("dint_T")), _p(out["dsub"]), _p(out["valid"]),
+                                   _p(out["disp"]), _p(ws), plan.workspace_bytes, _stream()))
+    return out
+
+
+def road_fit_from_bytes(buf: torch.Tensor) -> dict:
+    raw = bytes(buf.cpu().numpy().tobytes())
+    f = RoadFit.from_buffer_copy(raw)
+    return dict(psi=f.psi, alpha0=f.alpha0, alpha1=f.alpha1, e_min=f.e_min,
+                plane=tuple(f.plane), n_points=f.n_points, iters=f.iters,
+                converged=bool(f.converged), flat=bool(f.flat))
+
+
+def road_transform(plan: Plan, disp, mask=None, psi_init=0.0, lambda0=LAMBDA0,
+                   delta_psi=DELTA_PSI, max_iter=100, delta_t=0.0, fit_buf=None,
+                   out=None, read_fit=True):
+    """Roll fit + disparity transformation; returns (fit dict or buffer, disp_t)."""
+    _need(disp, torch.float32, (plan.H, plan.W), "disp")
+    if mask is not None:
+        _need(mask, torch.uint8, (plan.H, plan.W), "mask")
+    dev = disp.device
+    if fit_buf is None:
+        fit_buf = torch.empty(ctypes.sizeof(RoadFit), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = torch.empty_like(disp)
+    ws = plan.workspace(dev)
+    check(_lib.load().stereo_road_transform(
+        plan.handle, _p(disp), _p(mask), float(psi_init), float(lambda0), float(delta_psi),
+        int(max_iter), float(delta_t), _p(fit_buf), _p(out), _p(ws), plan.workspace_bytes,
+        _stream()))
+    return (road_fit_from_bytes(fit_buf) if read_fit else fit_buf), out

@@ -1,0 +1,91 @@
+// Internal declarations shared by the library's host and device sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/stereo.h"
+
+namespace stereo {
+
+// Set the thread-local error message and return the status.
+stereo_status fail(stereo_status s, const char* fmt, ...);
+// Map a HIP error (after a launch) to a status; hipSuccess -> STEREO_OK.
+stereo_status hip_check(hipError_t e, const char* what);
+
+constexpr float kOffset = 128.0f;   // NCC is offset invariant; centring the
+                                    // intensities keeps FP32 block sums exact
+constexpr float kFlatVar = 1e-6f;   // block variance (gray^2) below which the
+                                    // NCC is undefined and the cost is 1
+constexpr float kFarGuide = 1e30f;  // guide value outside the image: weight 0
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Derived sizes and the workspace layout of a plan.
+struct Plan {
+  stereo_params p;
+  int W, H, D, r, R;
+  int stats_w;        // block-statistics map width: columns [-r, W + r)
+  int cw;             // row pitch of the internal cost volume (>= W + D - 1)
+  size_t off_tarw, off_stats, off_cvol, off_dT, off_dsub, off_road;
+  size_t ws_bytes;
+  int road_blocks;    // partial-sum blocks of the road moments
+};
+
+// Float view of a few plan parameters, precomputed on the host.
+struct Consts {
+  float ks2;          // log2(e) / sigma_s^2
+  float kr2;          // log2(e) / sigma_r^2
+};
+Consts consts_of(const Plan& P);
+
+// ---- kernel launchers (each returns hipGetLastError after the launch) ----
+hipError_t launch_warp(const Plan& P, const void* tar, float* tar_w,
+                       hipStream_t s);
+
+// mu / 1/sigma of (I - 128) over the clamped (2r+1)^2 block centred at every
+// column x in [-r, W + r) and row y; isd = 0 marks a flat block.
+hipError_t launch_block_stats(const Plan& P, const void* img, stereo_dtype dt,
+                              int64_t pitch, float* mu, float* isd,
+                              hipStream_t s);
+
+// C[d][y][x], x in [0, out_w): anchor 0 compares the ref block at x with the
+// tar_w block at x - d; anchor 1 the ref block at x + d with tar_w at x.
+// ref statistics in (muX, isdX), tar_w statistics in (muY, isdY).
+hipError_t launch_ncc(const Plan& P, const void* ref, const float* tar_w,
+                      const float* muX, const float* isdX, const float* muY,
+                      const float* isdY, float* C, int out_w, int64_t out_pitch,
+                      int64_t out_slice, int anchor, hipStream_t s);
+
+struct BilArgs {
+  const float* C;     // cost slices: C[d * c_slice + y * c_pitch + x + d*shift]
+  int64_t c_slice;
+  int64_t c_pitch;
+  int shift;          // 1: slice d is read from column x + d (target volume)
+  const void* guide;  // guide image
+  stereo_dtype guide_dt;
+  int64_t guide_pitch;
+  float* E;           // mode 0: aggregated volume [D][H][W]
+  int16_t* dint;      // mode 1: WTA level [H][W]
+  float* dsub;        // mode 1: sub-pixel level [H][W] (nullable)
+};
+// mode 0: write the normalised aggregated volume; mode 1: fused WTA and
+// sub-pixel refinement (the volume never leaves the chip).
+hipError_t launch_bilateral(const Plan& P, const BilArgs& a, int mode,
+                            hipStream_t s);
+
+hipError_t launch_wta(const Plan& P, const float* E, int16_t* dint,
+                      float* dsub, hipStream_t s);
+hipError_t launch_lr_check(const Plan& P, const int16_t* dR, const int16_t* dT,
+                           const float* dsub, uint8_t* valid, float* disp,
+                           hipStream_t s);
+
+hipError_t launch_road(const Plan& P, const float* disp, const uint8_t* mask,
+                       double psi0, double lambda0, double delta_psi,
+                       int max_iter, float delta_t, stereo_road_fit* fit,
+                       float* disp_t, double* partials, hipStream_t s);
+
+}  // namespace stereo

@@ -1,0 +1,85 @@
+// Disparity selection on a materialised aggregated volume (Sec. 3.2.2):
+// winner-take-all with the sub-pixel parabola of Eq. (13), and the
+// left-right check of Eq. (12) followed by the shift back to the full
+// disparity domain.
+#include "internal.h"
+
+namespace stereo {
+namespace {
+
+// One thread per pixel walks the levels in order; volume reads are
+// coalesced across the threads of a slice.
+__global__ void __launch_bounds__(256)
+wta_kernel(const float* __restrict__ E, int W, int H, int D,
+           int16_t* __restrict__ dint, float* __restrict__ dsub) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t HW = (int64_t)W * H;
+  if (p >= HW) return;
+  float bestE = 3.402823466e38f, Em = 0.0f, Ep = 0.0f, prev = 0.0f;
+  int bestD = 0;
+  for (int d = 0; d < D; ++d) {
+    const float e = E[(int64_t)d * HW + p];
+    if (d == bestD + 1) Ep = e;
+    if (e < bestE) { Em = prev; bestE = e; bestD = d; }
+    prev = e;
+  }
+  dint[p] = (int16_t)bestD;
+  if (dsub) {
+    float off = 0.0f;
+    if (bestD > 0 && bestD < D - 1) {
+      const float den = 2.0f * Em + 2.0f * Ep - 4.0f * bestE;
+      if (den > 0.0f) off = (Em - Ep) / den;
+    }
+    dsub[p] = (float)bestD + off;
+  }
+}
+
+// valid = (u - dR >= 0) && (dR - dT(u - dR))^2 <= delta_r;
+// disp = l - delta_p + d_road(u - l + delta_p, v), evaluated in FP64.
+__global__ void __launch_bounds__(256)
+lr_kernel(const int16_t* __restrict__ dR, const int16_t* __restrict__ dT,
+          const float* __restrict__ dsub, int W, int H, float lr_delta,
+          int use_lr, int persp, double delta_p, double c0, double c1, double c2,
+          uint8_t* __restrict__ valid, float* __restrict__ disp) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (u >= W) return;
+  const int64_t p = (int64_t)v * W + u;
+  const int d = dR[p];
+  const int x = u - d;
+  bool ok = x >= 0;
+  if (ok && use_lr) {
+    const float diff = (float)(d - (int)dT[(int64_t)v * W + x]);
+    ok = diff * diff <= lr_delta;
+  }
+  if (valid) valid[p] = ok ? 1 : 0;
+  if (disp) {
+    const double ell = dsub ? (double)dsub[p] : (double)d;
+    double out = ell;
+    if (persp) out = ell - delta_p + (c0 + c1 * ((double)u - ell + delta_p) + c2 * (double)v);
+    disp[p] = ok ? (float)out : __builtin_nanf("");
+  }
+}
+
+}  // namespace
+
+hipError_t launch_wta(const Plan& P, const float* E, int16_t* dint, float* dsub,
+                      hipStream_t s) {
+  const int64_t HW = (int64_t)P.W * P.H;
+  hipLaunchKernelGGL(wta_kernel, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, s,
+                     E, P.W, P.H, P.D, dint, dsub);
+  return hipGetLastError();
+}
+
+hipError_t launch_lr_check(const Plan& P, const int16_t* dR, const int16_t* dT,
+                           const float* dsub, uint8_t* valid, float* disp,
+                           hipStream_t s) {
+  const stereo_params& p = P.p;
+  hipLaunchKernelGGL(lr_kernel, dim3((P.W + 255) / 256, P.H), dim3(256), 0, s, dR, dT,
+                     dsub, P.W, P.H, p.lr_delta, (p.lr_check && dT) ? 1 : 0,
+                     p.perspective, p.perspective ? (double)p.delta_p : 0.0,
+                     p.plane[0], p.plane[1], p.plane[2], valid, disp);
+  return hipGetLastError();
+}
+
+}  // namespace stereo
