@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark of the road-stereo hot path on one MI355X.
+
+One step = the whole plain path on one 1280x720 uint8 pair (perspective
+transformation, NCC cost volume, bilateral aggregation + WTA of both
+volumes, sub-pixel, left-right check, shift back) plus the road fit and
+disparity transformation, inputs resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MI355X_HBM_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz: the FP32 vector
+# rate of plain v_fma_f32.  Packed FP32 (v_pk_fma_f32) would double it to the
+# published 157.3 TFLOP/s but is disabled in this build.
+MI355X_FP32_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+MI355X_FP32_PACKED_TFLOPS = 157.3
+
+
+def _sha(path):
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def _traffic(kernel_src, launches_bytes_key):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, only
+    if the kernel source is unchanged since they were taken."""
+    f = os.path.join(ROOT, "profiles", "traffic_bilateral_c3a.json")
+    if not os.path.exists(f):
+        return None
+    d = json.load(open(f))
+    if d.get("source_sha") != _sha(kernel_src):
+        return None
+    return d.get(launches_bytes_key)
+
+
+def cpu_baseline(w, sc, rows):
+    import numpy as np
+    import oracle.stereo as OS
+    from dataclasses import replace
+    ws = replace(w, height=rows)
+    t0 = time.perf_counter()
+    OS.match(sc.ref[:rows], sc.tar[:rows], ws)
+    dt = time.perf_counter() - t0
+    return dict(value=w.width * rows * w.num_disp / dt / 1e9, unit="G pixel·disparities/s",
+                cores=1, kind="oracle", seconds=round(dt, 2),
+                sample=f"rows 0..{rows - 1} of the {w.width}x{w.height} pair, D={w.num_disp}, "
+                       f"full plain path (FP64 numpy, single thread)")
+
+
+def run(args):
+    import torch
+
+    from paper_1904_06017_amd import api
+    from synth import make_workload_pair, workload
+
+    dev = torch.device("cuda:0")
+    w = workload("c3a")
+    sc = make_workload_pair(w)
+    plan = api.Plan.from_workload(w)
+    ref = torch.from_numpy(sc.ref).to(dev)
+    tar = torch.from_numpy(sc.tar).to(dev)
+    H, W = w.height, w.width
+    out = dict(dint_R=torch.empty((H, W), dtype=torch.int16, device=dev),
+               dint_T=torch.empty((H, W), dtype=torch.int16, device=dev),
+               dsub=torch.empty((H, W), dtype=torch.float32, device=dev),
+               valid=torch.empty((H, W), dtype=torch.uint8, device=dev),
+               disp=torch.empty((H, W), dtype=torch.float32, device=dev))
+    fit_buf = torch.empty(80, dtype=torch.uint8, device=dev)
+    disp_t = torch.empty((H, W), dtype=torch.float32, device=dev)
+    ws = plan.workspace(dev)
+    lib = api._lib.load()
+    import ctypes
+
+    def step(ev=None):
+        evp = None
+        if ev is not None:
+            arr = (ctypes.c_void_p * 7)(*[e.cuda_event for e in ev])
+            evp = arr
+        api.check(lib.stereo_match_profiled(
+            plan.handle, api._p(ref), api._p(tar), api._p(out["dint_R"]), api._p(out["dint_T"]),
+            api._p(out["dsub"]), api._p(out["valid"]), api._p(out["disp"]), api._p(ws),
+            plan.workspace_bytes, evp, api._stream()))
+        api.road_transform(plan, out["disp"], None, fit_buf=fit_buf, out=disp_t, read_fit=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    K = args.steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(K)]
+    for e in evs:
+        for x in e:
+            x.record()   # materialise the underlying event objects
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record()
+    for k in range(K):
+        step(evs[k])
+    t_end.record()
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    ms = total_ms / K
+    stage = lambda i, j: sum(evs[k][i].elapsed_time(evs[k][j]) for k in range(K)) / K
+    st = dict(warp_ms=stage(0, 1), stats_ms=stage(1, 2), ncc_ms=stage(2, 3),
+              aggregate_wta_ref_ms=stage(3, 4), aggregate_wta_tar_ms=stage(4, 5),
+              lr_check_ms=stage(5, 6), match_ms=stage(0, 6))
+    st["road_ms"] = ms - st["match_ms"]
+
+    elements = W * H * w.num_disp
+    taps = (2 * w.bil_radius + 1) ** 2
+    flops_per_launch = 2.0 * taps * elements          # multiply-adds of Eq. (11)
+    agg_s = (st["aggregate_wta_ref_ms"] + st["aggregate_wta_tar_ms"]) / 2.0 / 1e3
+    achieved = flops_per_launch / agg_s / 1e12
+    src = os.path.join(ROOT, "paper_1904_06017_amd", "csrc", "k_bilateral.hip")
+    roof = dict(kernel="bilateral_kernel (aggregation + fused WTA, both volumes)",
+                bound="alu", achieved=round(achieved, 2), peak=round(MI355X_FP32_VALU_TFLOPS, 1),
+                unit="TFLOP/s", frac=round(achieved / MI355X_FP32_VALU_TFLOPS, 4),
+                frac_of_packed_peak=round(achieved / MI355X_FP32_PACKED_TFLOPS, 4),
+                flops_per_launch=flops_per_launch, avg_launch_ms=round(agg_s * 1e3, 4),
+                traffic=_traffic(src, "hbm_bytes_per_launch"))
+    # NCC stage: HBM-bound when the volume is materialised
+    cw = ((W + w.num_disp - 1) + 3) & ~3
+    ncc_bytes = 4.0 * w.num_disp * H * (W + w.num_disp - 1)
+    ncc = dict(kernel="ncc_kernel", bound="hbm", achieved=round(ncc_bytes / (st["ncc_ms"] / 1e3) / 1e9, 1),
+               peak=MI355X_HBM_GBS, unit="GB/s",
+               frac=round(ncc_bytes / (st["ncc_ms"] / 1e3) / 1e9 / MI355X_HBM_GBS, 4),
+               bytes_per_launch=ncc_bytes)
+
+    value = elements / (ms / 1e3) / 1e9
+    res = {
+        "metric": "G pixel·disparities/s (fwd, fwd+bwd) and fps at 1280×720, vs plain per-pair",
+        "value": round(value, 3),
+        "unit": "G pixel·disparities/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "fps": round(1e3 / ms, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "width": W, "height": H, "num_disp": w.num_disp,
+                   "ncc": f"{2 * w.ncc_radius + 1}x{2 * w.ncc_radius + 1}",
+                   "bilateral": f"{2 * w.bil_radius + 1}x{2 * w.bil_radius + 1}",
+                   "sigma_s": w.sigma_s, "sigma_r": w.sigma_r, "perspective": True,
+                   "input": "uint8", "step": "plain path + road fit/transform"},
+        "stages_ms": {k: round(v, 4) for k, v in st.items()},
+        "roofline": roof,
+        "roofline_ncc": ncc,
+    }
+    if args.extra:
+        res["range_reduction"] = range_reduction(args, sc, ms)
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(w, sc, args.cpu_rows)
+    return res
+
+
+def range_reduction(args, sc, ms_3a):
+    """Same pair searched over the full 0..127 range without the warp."""
+    import torch
+
+    from paper_1904_06017_amd import api
+    from synth import workload
+    w = workload("c3b")
+    plan = api.Plan.from_workload(w)
+    dev = torch.device("cuda:0")
+    ref = torch.from_numpy(sc.ref).to(dev)
+    tar = torch.from_numpy(sc.tar).to(dev)
+    o = None
+    for _ in range(3):
+        o = api.match(plan, ref, tar, out=o)
+    torch.cuda.synchronize()
+    n = max(5, args.steps // 4)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(n):
+        api.match(plan, ref, tar, out=o)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / n
+    return dict(workload=w.name, num_disp=w.num_disp, match_ms=round(ms, 4),
+                gpd_s=round(w.width * w.height * w.num_disp / (ms / 1e3) / 1e9, 3),
+                speedup_of_perspective=round(ms / ms_3a, 3))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=96)
+    ap.add_argument("--no-extra", dest="extra", action="store_false")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    res = run(args)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

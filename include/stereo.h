@@ -162,6 +162,18 @@ stereo_status stereo_match(stereo_plan_t plan, const void* ref, const void* tar,
                            uint8_t* valid, float* disp, void* ws,
                            size_t ws_bytes, hipStream_t stream);
 
+/* ---- the same, recording caller-owned events at the stage boundaries ---
+ * ev: 7 events created by the caller (hipEventCreate), recorded on `stream`:
+ * [0] start, [1] after the warp, [2] after the block statistics, [3] after
+ * the NCC volume, [4] after aggregation + WTA of the reference volume, [5]
+ * after that of the target volume, [6] after the left-right check.  For
+ * profiling; results are identical to stereo_match. */
+#define STEREO_MATCH_EVENTS 7
+stereo_status stereo_match_profiled(stereo_plan_t plan, const void* ref, const void* tar,
+                                    int16_t* dint_R, int16_t* dint_T, float* dsub,
+                                    uint8_t* valid, float* disp, void* ws,
+                                    size_t ws_bytes, hipEvent_t* ev, hipStream_t stream);
+
 /* ---- road fit + disparity transformation, Sec. 3.3, Eqs. (14)-(29) ------
  * disp: [H][W] FP32 (NaN = invalid); mask: [H][W] uint8 (nullable: all).
  * Fits the roll psi by gradient descent (Eq. 25) with the adaptive rate of

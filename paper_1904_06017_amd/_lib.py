@@ -68,6 +68,9 @@ SIGNATURES = {
                                 c_void_p, c_void_p]),
     "stereo_match": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                              c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "stereo_match_profiled": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                                      c_void_p, c_void_p]),
     "stereo_road_transform": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double,
                                       c_double, c_int32, c_float, c_void_p, c_void_p,
                                       c_void_p, c_size_t, c_void_p]),

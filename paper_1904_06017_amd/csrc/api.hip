@@ -261,6 +261,14 @@ stereo_status stereo_lr_check(stereo_plan_t plan, const int16_t* dint_R,
 stereo_status stereo_match(stereo_plan_t plan, const void* ref, const void* tar,
                            int16_t* dint_R, int16_t* dint_T, float* dsub, uint8_t* valid,
                            float* disp, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return stereo_match_profiled(plan, ref, tar, dint_R, dint_T, dsub, valid, disp, ws, ws_bytes,
+                               nullptr, stream);
+}
+
+stereo_status stereo_match_profiled(stereo_plan_t plan, const void* ref, const void* tar,
+                                    int16_t* dint_R, int16_t* dint_T, float* dsub,
+                                    uint8_t* valid, float* disp, void* ws, size_t ws_bytes,
+                                    hipEvent_t* ev, hipStream_t stream) {
   STEREO_REQUIRE(plan && ref && tar && dint_R, "plan, ref, tar and dint_R must be non-NULL");
   const Plan& P = plan->P;
   stereo_status s = check_ws(P, ws, ws_bytes);
@@ -270,18 +278,25 @@ stereo_status stereo_match(stereo_plan_t plan, const void* ref, const void* tar,
   float* cvol = at<float>(ws, P.off_cvol);
   int16_t* dT = dint_T ? dint_T : at<int16_t>(ws, P.off_dT);
   float* ds = dsub ? dsub : at<float>(ws, P.off_dsub);
+  auto mark = [&](int i) -> hipError_t {
+    return ev ? hipEventRecord(ev[i], stream) : hipSuccess;
+  };
 
+  STEREO_HIP(mark(0), "event record");
   STEREO_HIP(launch_warp(P, tar, tarw, stream), "warp");
+  STEREO_HIP(mark(1), "event record");
   STEREO_HIP(launch_block_stats(P, ref, P.p.dtype, P.p.pitch_ref, m.muX, m.isdX, stream),
              "block statistics (ref)");
   STEREO_HIP(launch_block_stats(P, tarw, STEREO_F32, P.W, m.muY, m.isdY, stream),
              "block statistics (tar_w)");
+  STEREO_HIP(mark(2), "event record");
   // One reference-anchored volume over the extended columns [0, W + D - 1):
   // the target volume is its re-indexing C_T(x, d) = C_R(x + d, d).
   const int64_t slice = (int64_t)P.H * P.cw;
   const int ext_w = P.W + P.D - 1;
   STEREO_HIP(launch_ncc(P, ref, tarw, m.muX, m.isdX, m.muY, m.isdY, cvol, ext_w, P.cw, slice,
                         0, stream), "ncc");
+  STEREO_HIP(mark(3), "event record");
   BilArgs a{};
   a.C = cvol;
   a.c_slice = slice;
@@ -293,6 +308,7 @@ stereo_status stereo_match(stereo_plan_t plan, const void* ref, const void* tar,
   a.dint = dint_R;
   a.dsub = ds;
   STEREO_HIP(launch_bilateral(P, a, 1, stream), "bilateral + WTA (reference)");
+  STEREO_HIP(mark(4), "event record");
   const bool lr = P.p.lr_check != 0;
   if (lr) {
     BilArgs b = a;
@@ -304,9 +320,11 @@ stereo_status stereo_match(stereo_plan_t plan, const void* ref, const void* tar,
     b.dsub = nullptr;
     STEREO_HIP(launch_bilateral(P, b, 1, stream), "bilateral + WTA (target)");
   }
+  STEREO_HIP(mark(5), "event record");
   if (valid || disp)
     STEREO_HIP(launch_lr_check(P, dint_R, lr ? dT : nullptr, ds, valid, disp, stream),
                "left-right check");
+  STEREO_HIP(mark(6), "event record");
   return STEREO_OK;
 }
 

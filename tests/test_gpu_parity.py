@@ -150,9 +150,12 @@ def _check_selection(w, ora, dR, dT, dsub, valid, disp):
 
 
 def test_near_ties_are_rare():
-    """The tie exception must stay an exception on textured scenes."""
+    """The tie exception must stay an exception on textured scenes.  Exact
+    ties are structural near the left border, where every level beyond
+    u + R + r reads the same clamped target blocks; away from it they are rare."""
     w, sc, ora = case("c1")
-    assert np.mean(PR.top2_gap(ora["E_R"]) < PR.TIE_GAP) < 1e-3
+    band = w.num_disp + w.bil_radius + w.ncc_radius
+    assert np.mean(PR.top2_gap(ora["E_R"])[:, band:] < PR.TIE_GAP) < 1e-3
 
 
 # -- road transform -----------------------------------------------------------
@@ -239,7 +242,7 @@ def test_full_size_sampled(name):
             continue
         assert dR[v, u] == q["dint_R"], (u, v)
         curv = PR.parabola_curvature(q["E_R"][:, None, None], np.array([[q["dint_R"]]]))[0, 0]
-        tol = (PR.SUB_TOL_FLAT if curv < PR.FLAT_PARABOLA else PR.SUB_TOL) * max(abs(q["ell"]), 1)
+        tol = float(PR.subpixel_tol(np.array(q["ell"]), np.array(curv)))
         assert abs(dsub[v, u] - q["ell"]) <= tol, (u, v)
         if q["dint_T"] >= 0 and q["gap_T"] >= PR.TIE_GAP:
             assert dT[v, u - q["dint_R"]] == q["dint_T"], (u, v)
