@@ -69,6 +69,9 @@ def run(args):
     w = workload("c3a")
     sc = make_workload_pair(w)
     plan = api.Plan.from_workload(w)
+    for kv in args.tune:
+        k, v = kv.split("=")
+        plan.set_tuning(k, int(v))
     ref = torch.from_numpy(sc.ref).to(dev)
     tar = torch.from_numpy(sc.tar).to(dev)
     H, W = w.height, w.width
@@ -155,6 +158,7 @@ def run(args):
                    "sigma_s": w.sigma_s, "sigma_r": w.sigma_r, "perspective": True,
                    "input": "uint8", "step": "plain path + road fit/transform"},
         "stages_ms": {k: round(v, 4) for k, v in st.items()},
+        "tuning": {k: plan.get_tuning(k) for k in ("agg_levels_u8", "agg_levels_f32")},
         "roofline": roof,
         "roofline_ncc": ncc,
     }
@@ -194,6 +198,19 @@ def range_reduction(args, sc, ms_3a):
                 speedup_of_perspective=round(ms / ms_3a, 3))
 
 
+def copy_calibration(mib):
+    """A plain device copy of known size, for scaling HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.rand(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
+                      "launches": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,7 +219,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=96)
     ap.add_argument("--no-extra", dest="extra", action="store_false")
+    ap.add_argument("--tune", action="append", default=[],
+                    help="plan tuning key=value (e.g. agg_levels_f32=16)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration_mib:
+        copy_calibration(args.copy_calibration_mib)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)

@@ -107,6 +107,15 @@ stereo_status stereo_plan_destroy(stereo_plan_t plan);
 stereo_status stereo_plan_workspace_bytes(stereo_plan_t plan, size_t* bytes);
 stereo_status stereo_plan_get_params(stereo_plan_t plan, stereo_params* out);
 
+/* ---- tuning knobs (host only) ---------------------------------------------
+ * Launch-shape choices that never change results.  Keys:
+ *   "agg_levels_u8", "agg_levels_f32": disparity levels staged per pass of
+ *   the aggregation kernel for 8-bit / float guides, 8 or 16 (default 8).
+ * Unknown keys and values give INVALID_ARGUMENT.  Not thread-safe against
+ * concurrent enqueues on the same plan. */
+stereo_status stereo_plan_set_tuning(stereo_plan_t plan, const char* key, int32_t value);
+stereo_status stereo_plan_get_tuning(stereo_plan_t plan, const char* key, int32_t* value);
+
 /* ---- perspective transformation, Sec. 3.1, Eq. (4) ----------------------
  * tar: [H][pitch_tar] of params.dtype.  tar_w: [H][W] FP32.
  * tar_w(x,v) = lerp of row v at X = x + delta_p - d_road(x + delta_p, v),

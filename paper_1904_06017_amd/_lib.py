@@ -58,6 +58,8 @@ SIGNATURES = {
     "stereo_plan_destroy": (c_int, [c_void_p]),
     "stereo_plan_workspace_bytes": (c_int, [c_void_p, POINTER(c_size_t)]),
     "stereo_plan_get_params": (c_int, [c_void_p, POINTER(StereoParams)]),
+    "stereo_plan_set_tuning": (c_int, [c_void_p, c_char_p, c_int32]),
+    "stereo_plan_get_tuning": (c_int, [c_void_p, c_char_p, POINTER(c_int32)]),
     "stereo_warp": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "stereo_cost_volume": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_size_t, c_void_p]),

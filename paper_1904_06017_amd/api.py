@@ -106,6 +106,14 @@ class Plan:
     def img_dtype(self):
         return torch.uint8 if self.params.dtype == _lib.U8 else torch.float32
 
+    def set_tuning(self, key: str, value: int):
+        check(_lib.load().stereo_plan_set_tuning(self._h, key.encode(), int(value)))
+
+    def get_tuning(self, key: str) -> int:
+        v = ctypes.c_int32()
+        check(_lib.load().stereo_plan_get_tuning(self._h, key.encode(), ctypes.byref(v)))
+        return int(v.value)
+
     def workspace(self, device="cuda"):
         if self._ws is None or self._ws.device != torch.device(device):
             self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)

@@ -83,6 +83,8 @@ stereo_status validate(const stereo_params* p) {
   if (!std::isfinite(p->delta_p) || !std::isfinite(p->plane[0]) ||
       !std::isfinite(p->plane[1]) || !std::isfinite(p->plane[2]))
     return fail(STEREO_ERR_INVALID_ARGUMENT, "delta_p and plane must be finite");
+  if ((int64_t)p->num_disp * p->height * ((int64_t)p->width + p->num_disp + 4) >= ((int64_t)1 << 31))
+    return fail(STEREO_ERR_UNSUPPORTED, "cost volume above 2^31 elements");
   if (p->perspective && !(std::fabs(p->plane[1]) < 0.5))
     return fail(STEREO_ERR_INVALID_ARGUMENT, "|plane c1| must be < 0.5 px/column");
   return STEREO_OK;
@@ -181,6 +183,25 @@ stereo_status stereo_plan_workspace_bytes(stereo_plan_t plan, size_t* bytes) {
   STEREO_REQUIRE(plan && bytes, "plan and bytes must be non-NULL");
   *bytes = plan->P.ws_bytes;
   return STEREO_OK;
+}
+
+stereo_status stereo_plan_set_tuning(stereo_plan_t plan, const char* key, int32_t value) {
+  STEREO_REQUIRE(plan && key, "plan and key must be non-NULL");
+  const std::string k(key);
+  if (k == "agg_levels_u8" || k == "agg_levels_f32") {
+    STEREO_REQUIRE(value == 8 || value == 16, "%s must be 8 or 16", key);
+    (k == "agg_levels_u8" ? plan->P.agg_levels_u8 : plan->P.agg_levels_f32) = value;
+    return STEREO_OK;
+  }
+  return fail(STEREO_ERR_INVALID_ARGUMENT, "unknown tuning key '%s'", key);
+}
+
+stereo_status stereo_plan_get_tuning(stereo_plan_t plan, const char* key, int32_t* value) {
+  STEREO_REQUIRE(plan && key && value, "plan, key and value must be non-NULL");
+  const std::string k(key);
+  if (k == "agg_levels_u8") { *value = plan->P.agg_levels_u8; return STEREO_OK; }
+  if (k == "agg_levels_f32") { *value = plan->P.agg_levels_f32; return STEREO_OK; }
+  return fail(STEREO_ERR_INVALID_ARGUMENT, "unknown tuning key '%s'", key);
 }
 
 stereo_status stereo_plan_get_params(stereo_plan_t plan, stereo_params* out) {

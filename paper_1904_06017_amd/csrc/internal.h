@@ -33,6 +33,9 @@ struct Plan {
   size_t off_tarw, off_stats, off_cvol, off_dT, off_dsub, off_road;
   size_t ws_bytes;
   int road_blocks;    // partial-sum blocks of the road moments
+  // tuning (stereo_plan_set_tuning): levels per aggregation pass by guide type
+  int agg_levels_u8 = 8;
+  int agg_levels_f32 = 8;
 };
 
 // Float view of a few plan parameters, precomputed on the host.

@@ -14,17 +14,34 @@
 //   * a thread owns PX horizontally adjacent pixels x DC levels in registers;
 //     every cost quad read from LDS feeds up to PX pixels, every weight feeds
 //     DC fused multiply-adds;
-//   * weights are computed in registers, w = exp2(sx(dx) + sy(dy) - kr2 dG^2)
-//     (the spatial factor of Eq. 31 and the range factor of Eq. 32 folded into
-//     one exponent); a guide of 1e30 outside the image gives weight 0.
+//   * weights are computed in registers.  For an 8-bit guide the range factor
+//     of Eq. (32) comes from a table over the 511 possible intensity
+//     differences, built in LDS by each workgroup (the paper keeps its tables
+//     in constant memory; LDS is the on-chip store with per-lane gathers on
+//     CDNA), times the spatial factor of Eq. (31):  w = T[dG] * ex(dx) * ey(dy).
+//     For a float guide, w = exp2(sx(dx) + sy(dy) - dG'^2) in one exponent,
+//     with the guide pre-scaled by sqrt(log2(e)) / sigma_r.
+//     Outside the image the guide is a sentinel that gives weight 0.
 // Taps are summed in raster order (dy outer, dx inner) for every pixel, so
 // the result does not depend on the tile shape.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace stereo {
 namespace {
 
 constexpr int kThreads = 256;
+
+// Range table for 8-bit guides: index 512 + G(p) - G(q); entries 257..767
+// hold exp(-dG^2 / sigma_r^2), entries 768..1023 are zero and catch the
+// out-of-image sentinel G(q) = -256 (every index stays inside the table, also
+// for the sentinel on the pixel side of tiles that overhang the image).  The
+// table sits at LDS address 0 so that a lookup is one subtraction and one
+// ds_read; the guide tile is kept as int16 (4 G, a byte offset).
+constexpr int kTabSize = 1024;
+constexpr int kTabCentre = 512;
+constexpr int kOutsideG = -256;
 
 template <int R, int PX, int DC, int TYT>
 struct BilGeom {
@@ -35,8 +52,17 @@ struct BilGeom {
   static constexpr int HY = TH + 2 * R;
   static constexpr int HXP = HX | 1;          // odd pitch in float4 units
   static constexpr int NQ = DC / 4;
-  static constexpr size_t lds_bytes =
-      sizeof(float4) * (size_t)NQ * HY * HXP + sizeof(float) * (size_t)HY * HX;
+  // LDS layout: [table (8-bit guide only)] [guide tile] [cost quads]
+  template <bool TAB>
+  static constexpr size_t tab_bytes() { return TAB ? sizeof(float) * kTabSize : 0; }
+  template <bool TAB>
+  static constexpr size_t guide_bytes() {
+    return ((TAB ? sizeof(int16_t) : sizeof(float)) * (size_t)HY * HX + 15) & ~size_t(15);
+  }
+  template <bool TAB>
+  static constexpr size_t lds_bytes() {
+    return tab_bytes<TAB>() + guide_bytes<TAB>() + sizeof(float4) * (size_t)NQ * HY * HXP;
+  }
 };
 
 template <typename G>
@@ -52,30 +78,62 @@ bilateral_kernel(const float* __restrict__ C, int64_t c_slice, int64_t c_pitch,
                  float* __restrict__ E, int16_t* __restrict__ dint,
                  float* __restrict__ dsub) {
   using Gm = BilGeom<R, PX, DC, TYT>;
+  constexpr bool TAB = std::is_same<GT, uint8_t>::value;
   extern __shared__ float4 lds4[];
-  float4* Cs = lds4;                                        // [NQ][HY][HXP]
-  float* Gs = reinterpret_cast<float*>(lds4 + Gm::NQ * Gm::HY * Gm::HXP);  // [HY][HX]
+  char* lds = reinterpret_cast<char*>(lds4);
+  float* Tab = reinterpret_cast<float*>(lds);                             // [kTabSize]
+  float* Gs = reinterpret_cast<float*>(lds + Gm::template tab_bytes<TAB>());  // [HY][HX]
+  int16_t* Gsi = reinterpret_cast<int16_t*>(Gs);            // 4 G for 8-bit guides
+  float4* Cs = reinterpret_cast<float4*>(lds + Gm::template tab_bytes<TAB>() +
+                                         Gm::template guide_bytes<TAB>());  // [NQ][HY][HXP]
 
   const int t = threadIdx.x;
   const int ty = t % TYT;
   const int tx = t / TYT;
   const int x0 = blockIdx.x * Gm::TW;
   const int y0 = blockIdx.y * Gm::TH;
+  const float kr = sqrtf(kr2);
 
   for (int i = t; i < Gm::HY * Gm::HX; i += kThreads) {
     const int yy = i / Gm::HX, xx = i - yy * Gm::HX;
     const int gy = y0 - R + yy, gx = x0 - R + xx;
-    Gs[i] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? guide_at(guide, g_pitch, gx, gy)
-                                                     : kFarGuide;
+    const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+    if (TAB)
+      Gsi[i] = (int16_t)(4 * (in ? (int)guide[(int64_t)gy * g_pitch + gx] : kOutsideG));
+    else  // pre-scaled by sqrt(kr2): the range exponent is then -(G'(p) - G'(q))^2
+      Gs[i] = in ? guide_at(guide, g_pitch, gx, gy) * kr : kFarGuide;
+  }
+  if (TAB) {
+    for (int i = t; i < kTabSize; i += kThreads) {
+      const float dg = (float)(i - kTabCentre);
+      Tab[i] = (i >= 768) ? 0.0f : __builtin_amdgcn_exp2f(-dg * dg * kr2);
+    }
   }
   __syncthreads();
 
   float gp[PX];
+  int gp4[PX];
 #pragma unroll
-  for (int k = 0; k < PX; ++k) gp[k] = Gs[(ty + R) * Gm::HX + tx * PX + k + R];
+  for (int k = 0; k < PX; ++k) {
+    const int idx = (ty + R) * Gm::HX + tx * PX + k + R;
+    if (TAB) {
+      gp[k] = 0.0f;
+      gp4[k] = (int)Gsi[idx] + 4 * kTabCentre;
+    } else {
+      gp[k] = Gs[idx];
+      gp4[k] = 0;
+    }
+  }
   float sx[2 * R + 1];
 #pragma unroll
-  for (int j = 0; j <= 2 * R; ++j) sx[j] = -(float)((j - R) * (j - R)) * ks2;
+  for (int j = 0; j <= 2 * R; ++j) {
+    sx[j] = -(float)((j - R) * (j - R)) * ks2;
+    if (TAB) sx[j] = __builtin_amdgcn_exp2f(sx[j]);        // spatial factor e_x
+  }
+  // per-pixel table row: lookup address = tp[k] - 4 G(q), one subtraction
+  const char* tp[PX];
+#pragma unroll
+  for (int k = 0; k < PX; ++k) tp[k] = reinterpret_cast<const char*>(Tab) + gp4[k];
 
   float wsum[PX];
   float rinv[PX];
@@ -89,23 +147,36 @@ bilateral_kernel(const float* __restrict__ C, int64_t c_slice, int64_t c_pitch,
     bestE[k] = 3.402823466e38f; Em[k] = 0.0f; Ep[k] = 0.0f; prev[k] = 0.0f; bestD[k] = 0;
   }
 
+  // element step from level d to d + 1 (the target volume also moves one
+  // column to the right per level)
+  const uint32_t step = (uint32_t)c_slice + (uint32_t)shift;
   for (int d0 = 0; d0 < D; d0 += DC) {
-    // ---- stage the cost halo of this chunk: quads of 4 consecutive levels
-    for (int i = t; i < Gm::NQ * Gm::HY * Gm::HX; i += kThreads) {
-      const int q = i / (Gm::HY * Gm::HX);
-      const int rem = i - q * Gm::HY * Gm::HX;
-      const int yy = rem / Gm::HX, xx = rem - yy * Gm::HX;
-      const int gy = y0 - R + yy, gx = x0 - R + xx;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-        const int d = d0 + 4 * q;
-        const float* base = C + (int64_t)gy * c_pitch + gx;
-        if (d + 0 < D) v.x = base[(int64_t)(d + 0) * c_slice + (d + 0) * shift];
-        if (d + 1 < D) v.y = base[(int64_t)(d + 1) * c_slice + (d + 1) * shift];
-        if (d + 2 < D) v.z = base[(int64_t)(d + 2) * c_slice + (d + 2) * shift];
-        if (d + 3 < D) v.w = base[(int64_t)(d + 3) * c_slice + (d + 3) * shift];
+    // ---- stage the cost halo of this chunk: quads of 4 consecutive levels.
+    // Lanes run along columns (coalesced loads), the four waves along rows;
+    // offsets are 32-bit from a uniform base (SGPR-based global loads).
+    {
+      const int col = t & 63;
+      const int gx = x0 - R + col;
+      const bool colok = col < Gm::HX && gx >= 0 && gx < W;
+      for (int yy = t >> 6; yy < Gm::HY; yy += kThreads / 64) {
+        if (col >= Gm::HX) continue;
+        const int gy = y0 - R + yy;
+        const bool ok = colok && gy >= 0 && gy < H;
+        const uint32_t rowoff = ok ? (uint32_t)gy * (uint32_t)c_pitch + (uint32_t)gx : 0u;
+#pragma unroll
+        for (int q = 0; q < Gm::NQ; ++q) {
+          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (ok) {
+            const int d = d0 + 4 * q;
+            const uint32_t o = rowoff + (uint32_t)d * step;
+            if (d + 0 < D) v.x = C[o];
+            if (d + 1 < D) v.y = C[o + step];
+            if (d + 2 < D) v.z = C[o + 2 * step];
+            if (d + 3 < D) v.w = C[o + 3 * step];
+          }
+          Cs[(q * Gm::HY + yy) * Gm::HXP + col] = v;
+        }
       }
-      Cs[(q * Gm::HY + yy) * Gm::HXP + xx] = v;
     }
     __syncthreads();
 
@@ -119,8 +190,40 @@ bilateral_kernel(const float* __restrict__ C, int64_t c_slice, int64_t c_pitch,
     for (int dy = 0; dy <= 2 * R; ++dy) {
       const int row = ty + dy;
       const float sy = -(float)((dy - R) * (dy - R)) * ks2;
+      float wx[2 * R + 1];                       // 8-bit guide: e_y * e_x(dx)
+      if (TAB) {
+        const float ey = __builtin_amdgcn_exp2f(sy);
+#pragma unroll
+        for (int j = 0; j <= 2 * R; ++j) wx[j] = ey * sx[j];
+      }
       const float4* crow = Cs + row * Gm::HXP + tx * PX;
       const float* grow = Gs + row * Gm::HX + tx * PX;
+      const int16_t* growi = Gsi + row * Gm::HX + tx * PX;
+      // weights of this tap row first: the lookups / exponentials are
+      // independent of each other and of the cost reads below
+      float wr[PX][2 * R + 1];
+#pragma unroll
+      for (int xx = 0; xx < PX + 2 * R; ++xx) {
+        const float gq = TAB ? 0.0f : grow[xx];
+        const int gq4 = TAB ? (int)growi[xx] : 0;
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+          const int dx = xx - k;
+          if (dx < 0 || dx > 2 * R) continue;
+          if (TAB) {
+            wr[k][dx] = *reinterpret_cast<const float*>(tp[k] - gq4) * wx[dx];
+          } else {
+            const float g = gp[k] - gq;
+            wr[k][dx] = __builtin_amdgcn_exp2f(fmaf(-g, g, sy + sx[dx]));
+          }
+        }
+      }
+      if (MODE == 0 && first) {
+#pragma unroll
+        for (int k = 0; k < PX; ++k)
+#pragma unroll
+          for (int dx = 0; dx <= 2 * R; ++dx) wsum[k] += wr[k][dx];
+      }
 #pragma unroll
       for (int xx = 0; xx < PX + 2 * R; ++xx) {
         float cv[DC];
@@ -129,14 +232,11 @@ bilateral_kernel(const float* __restrict__ C, int64_t c_slice, int64_t c_pitch,
           const float4 v = crow[q * Gm::HY * Gm::HXP + xx];
           cv[4 * q + 0] = v.x; cv[4 * q + 1] = v.y; cv[4 * q + 2] = v.z; cv[4 * q + 3] = v.w;
         }
-        const float gq = grow[xx];
 #pragma unroll
         for (int k = 0; k < PX; ++k) {
           const int dx = xx - k;
           if (dx < 0 || dx > 2 * R) continue;
-          const float g = gp[k] - gq;
-          const float w = __builtin_amdgcn_exp2f(fmaf(g * g, -kr2, sy + sx[dx]));
-          if (MODE == 0 && first) wsum[k] += w;
+          const float w = wr[k][dx];
 #pragma unroll
           for (int j = 0; j < DC; ++j) acc[k][j] = fmaf(w, cv[j], acc[k][j]);
         }
@@ -204,30 +304,37 @@ template <int R, int PX, int DC, int TYT, typename GT, int MODE>
 hipError_t launch_one(const Plan& P, const BilArgs& a, hipStream_t s) {
   using Gm = BilGeom<R, PX, DC, TYT>;
   auto kern = bilateral_kernel<R, PX, DC, TYT, GT, MODE>;
+  constexpr size_t lds = Gm::template lds_bytes<std::is_same<GT, uint8_t>::value>();
   static bool attr_set = false;       // per instantiation; idempotent
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)Gm::lds_bytes);
+                                       (int)lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   dim3 grid((P.W + Gm::TW - 1) / Gm::TW, (P.H + Gm::TH - 1) / Gm::TH);
   const Consts c = consts_of(P);
-  hipLaunchKernelGGL(kern, grid, dim3(kThreads), Gm::lds_bytes, s, a.C, a.c_slice,
+  hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, a.C, a.c_slice,
                      a.c_pitch, a.shift, (const GT*)a.guide, a.guide_pitch, P.W, P.H,
                      P.D, c.ks2, c.kr2, a.E, a.dint, a.dsub);
   return hipGetLastError();
 }
 
-template <int R>
-hipError_t launch_r(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
-  constexpr int PX = 4, DC = 8, TYT = 32;
+template <int R, int DC>
+hipError_t launch_rd(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
+  constexpr int PX = 4, TYT = 32;
   if (a.guide_dt == STEREO_U8)
     return mode == 0 ? launch_one<R, PX, DC, TYT, uint8_t, 0>(P, a, s)
                      : launch_one<R, PX, DC, TYT, uint8_t, 1>(P, a, s);
   return mode == 0 ? launch_one<R, PX, DC, TYT, float, 0>(P, a, s)
                    : launch_one<R, PX, DC, TYT, float, 1>(P, a, s);
+}
+
+template <int R>
+hipError_t launch_r(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
+  const int dc = a.guide_dt == STEREO_U8 ? P.agg_levels_u8 : P.agg_levels_f32;
+  return dc == 16 ? launch_rd<R, 16>(P, a, mode, s) : launch_rd<R, 8>(P, a, mode, s);
 }
 
 }  // namespace

@@ -93,79 +93,149 @@ block_stats_kernel(const T* __restrict__ img, int64_t pitch, int W, int H, int r
 
 // NCC cost, Eq. (8), in its equivalent 1 - NCC form on offset intensities:
 //   C = 1 - (S/n - muX muY) / (sdX sdY),  S = sum over the block of X' Y'.
-// One workgroup covers NC_TX outputs x NC_TY rows x NC_DC levels.  The
-// cross sums are separable: vertical sums of products first (fixed order
-// i = 0..2r), then horizontal sums (fixed order j = 0..2r); the result is
-// independent of the tiling.
-constexpr int NC_TX = 64, NC_TY = 16, NC_DC = 8;
+// A workgroup covers NC_TX = 64 output columns (one per lane) x NC_TY rows x
+// NC_DC levels (NC_DW per wave).  Each lane walks down its column: for every
+// input row it forms the horizontal sum of the 2r+1 products (fixed order
+// j = -r..r) and keeps the last 2r+1 row sums in a register ring; the block
+// sum is the fixed-order sum of that ring (i = -r..r).  So every output is
+// the same expression whatever the tiling.
+//
+// The unshifted operand A (X' for anchor 0, Y' for anchor 1) and the
+// level-shifted operand B are staged in LDS with clamped reads.
+constexpr int NC_TX = 64, NC_TY = 32, NC_DC = 16, NC_DW = 4;
 
-template <typename T>
+template <int r>
+struct NccGeom {
+  static constexpr int K = 2 * r + 1;
+  static constexpr int ROWS = NC_TY + 2 * r;
+  static constexpr int AW = NC_TX + 2 * r;
+  static constexpr int BW = NC_TX + 2 * r + NC_DC - 1;
+  static constexpr size_t lds_bytes = sizeof(float) * (size_t)ROWS * (AW + BW);
+};
+
+template <int r, typename T>
 __global__ void __launch_bounds__(256)
 ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
-           const float* __restrict__ tarw, int W, int H, int D, int r,
+           const float* __restrict__ tarw, int W, int H, int D,
            const float* __restrict__ muX, const float* __restrict__ isdX,
            const float* __restrict__ muY, const float* __restrict__ isdY,
            float* __restrict__ C, int out_w, int64_t out_pitch,
            int64_t out_slice, int anchor) {
+  using G = NccGeom<r>;
+  constexpr int K = G::K;
   extern __shared__ float sm[];
-  const int k = 2 * r + 1;
-  const int tw = NC_TX + 2 * r + NC_DC - 1;     // tile width (both images)
-  const int th = NC_TY + 2 * r;
-  const int vw = NC_TX + 2 * r;                 // vertical-sum row width
-  float* Xs = sm;
-  float* Ys = Xs + th * tw;
-  float* Vs = Ys + th * tw;                     // [NC_DC][NC_TY][vw]
+  float* As = sm;                         // [ROWS][AW]
+  float* Bs = sm + G::ROWS * G::AW;       // [ROWS][BW]
   const int x0 = blockIdx.x * NC_TX;
   const int y0 = blockIdx.y * NC_TY;
   const int d0 = blockIdx.z * NC_DC;
   const int SW = W + 2 * r;
-  // column origins (image coordinates) of the two tiles
-  //   anchor 0: X at x + j - r,      Y at x - d + j - r
-  //   anchor 1: X at x + d + j - r,  Y at x + j - r
-  const int xoX = anchor ? x0 - r + d0 : x0 - r;
-  const int xoY = anchor ? x0 - r : x0 - r - d0 - (NC_DC - 1);
-  for (int i = threadIdx.x; i < th * tw; i += blockDim.x) {
-    const int yy = i / tw, xx = i - yy * tw;
+  // image column of A[.][0] and B[.][0]
+  //   anchor 0: A = X' at x + j - r, B = Y' at x - d + j - r
+  //   anchor 1: A = Y' at x + j - r, B = X' at x + d + j - r
+  const int axo = x0 - r;
+  const int bxo = anchor ? x0 - r + d0 : x0 - r - d0 - (NC_DC - 1);
+  for (int i = threadIdx.x; i < G::ROWS * G::BW; i += blockDim.x) {
+    const int yy = i / G::BW, xx = i - yy * G::BW;
     const int gy = min(max(y0 - r + yy, 0), H - 1);
-    const int gxX = min(max(xoX + xx, 0), W - 1);
-    const int gxY = min(max(xoY + xx, 0), W - 1);
-    Xs[i] = ld(ref + (int64_t)gy * ref_pitch + gxX) - kOffset;
-    Ys[i] = tarw[(int64_t)gy * W + gxY] - kOffset;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < NC_DC * NC_TY * vw; i += blockDim.x) {
-    const int dc = i / (NC_TY * vw);
-    const int rem = i - dc * NC_TY * vw;
-    const int y = rem / vw, xx = rem - y * vw;
-    const int cx = anchor ? xx + dc : xx;
-    const int cy = anchor ? xx : xx + (NC_DC - 1 - dc);
-    float s = 0.0f;
-    for (int a = 0; a < k; ++a) s = fmaf(Xs[(y + a) * tw + cx], Ys[(y + a) * tw + cy], s);
-    Vs[i] = s;
-  }
-  __syncthreads();
-  const float inv_n = 1.0f / (float)(k * k);
-  for (int i = threadIdx.x; i < NC_DC * NC_TY * NC_TX; i += blockDim.x) {
-    const int dc = i / (NC_TY * NC_TX);
-    const int rem = i - dc * NC_TY * NC_TX;
-    const int y = rem / NC_TX, xo = rem - y * NC_TX;
-    const int d = d0 + dc, gy = y0 + y, gx = x0 + xo;
-    if (d >= D || gy >= H || gx >= out_w) continue;
-    const float* vrow = Vs + (dc * NC_TY + y) * vw + xo;
-    float S = 0.0f;
-    for (int a = 0; a < k; ++a) S += vrow[a];
-    // statistics at the block centres, clamped to the map's column range
-    const int cxX = min(max(anchor ? gx + d : gx, -r), W - 1 + r) + r;
-    const int cxY = min(max(anchor ? gx : gx - d, -r), W - 1 + r) + r;
-    const float ix = isdX[(int64_t)gy * SW + cxX];
-    const float iy = isdY[(int64_t)gy * SW + cxY];
-    float c = 1.0f;
-    if (ix != 0.0f && iy != 0.0f) {
-      const float cov = fmaf(S, inv_n, -muX[(int64_t)gy * SW + cxX] * muY[(int64_t)gy * SW + cxY]);
-      c = 1.0f - cov * ix * iy;
+    const int gxb = min(max(bxo + xx, 0), W - 1);
+    Bs[i] = anchor ? ld(ref + (int64_t)gy * ref_pitch + gxb) - kOffset
+                   : tarw[(int64_t)gy * W + gxb] - kOffset;
+    if (xx < G::AW) {
+      const int gxa = min(max(axo + xx, 0), W - 1);
+      As[yy * G::AW + xx] = anchor ? tarw[(int64_t)gy * W + gxa] - kOffset
+                                   : ld(ref + (int64_t)gy * ref_pitch + gxa) - kOffset;
     }
-    C[(int64_t)d * out_slice + (int64_t)gy * out_pitch + gx] = c;
   }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int x = x0 + lane;
+  int boff[NC_DW];
+#pragma unroll
+  for (int k = 0; k < NC_DW; ++k) {
+    const int dc = wave * NC_DW + k;
+    boff[k] = anchor ? dc : (NC_DC - 1 - dc);
+  }
+  const float inv_n = 1.0f / (float)(K * K);
+  float ring[NC_DW][K];
+#pragma unroll
+  for (int k = 0; k < NC_DW; ++k)
+#pragma unroll
+    for (int i = 0; i < K; ++i) ring[k][i] = 0.0f;
+
+  for (int yb = 0; yb < G::ROWS; yb += K) {
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      const int yy = yb + s;
+      if (yy < G::ROWS) {
+        float a[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) a[j] = As[yy * G::AW + lane + j];
+#pragma unroll
+        for (int k = 0; k < NC_DW; ++k) {
+          const float* brow = Bs + yy * G::BW + lane + boff[k];
+          float h = a[0] * brow[0];
+#pragma unroll
+          for (int j = 1; j < K; ++j) h = fmaf(a[j], brow[j], h);
+          ring[k][s] = h;
+        }
+        const int y = y0 + yy - 2 * r;        // output row completed by this input row
+        if (yy >= 2 * r && y < H && x < out_w) {
+#pragma unroll
+          for (int k = 0; k < NC_DW; ++k) {
+            const int d = d0 + wave * NC_DW + k;
+            if (d >= D) continue;
+            // rows y-r .. y+r sit in ring slots (s+1) .. (s+K) mod K, in order
+            float S = ring[k][(s + 1) % K];
+#pragma unroll
+            for (int i = 2; i <= K; ++i) S += ring[k][(s + i) % K];
+            const int cxX = min(max(anchor ? x + d : x, -r), W - 1 + r) + r;
+            const int cxY = min(max(anchor ? x : x - d, -r), W - 1 + r) + r;
+            const int64_t rowo = (int64_t)y * SW;
+            const float ix = isdX[rowo + cxX];
+            const float iy = isdY[rowo + cxY];
+            float c = 1.0f;
+            if (ix != 0.0f && iy != 0.0f) {
+              const float cov = fmaf(S, inv_n, -muX[rowo + cxX] * muY[rowo + cxY]);
+              c = 1.0f - cov * ix * iy;
+            }
+            C[(int64_t)d * out_slice + (int64_t)y * out_pitch + x] = c;
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int r, typename T>
+hipError_t launch_ncc_r(const Plan& P, const T* ref, const float* tar_w, const float* muX,
+                        const float* isdX, const float* muY, const float* isdY, float* C,
+                        int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
+                        hipStream_t s) {
+  dim3 grid((out_w + NC_TX - 1) / NC_TX, (P.H + NC_TY - 1) / NC_TY,
+            (P.D + NC_DC - 1) / NC_DC);
+  hipLaunchKernelGGL((ncc_kernel<r, T>), grid, dim3(256), NccGeom<r>::lds_bytes, s, ref,
+                     P.p.pitch_ref, tar_w, P.W, P.H, P.D, muX, isdX, muY, isdY, C, out_w,
+                     out_pitch, out_slice, anchor);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ncc_t(const Plan& P, const T* ref, const float* tar_w, const float* muX,
+                        const float* isdX, const float* muY, const float* isdY, float* C,
+                        int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
+                        hipStream_t s) {
+#define NCC_CASE(R_) \
+  case R_: return launch_ncc_r<R_, T>(P, ref, tar_w, muX, isdX, muY, isdY, C, out_w, \
+                                      out_pitch, out_slice, anchor, s);
+  switch (P.r) {
+    NCC_CASE(1) NCC_CASE(2) NCC_CASE(3) NCC_CASE(4)
+    NCC_CASE(5) NCC_CASE(6) NCC_CASE(7) NCC_CASE(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef NCC_CASE
 }
 
 }  // namespace
@@ -203,20 +273,11 @@ hipError_t launch_ncc(const Plan& P, const void* ref, const float* tar_w,
                       const float* muX, const float* isdX, const float* muY,
                       const float* isdY, float* C, int out_w, int64_t out_pitch,
                       int64_t out_slice, int anchor, hipStream_t s) {
-  dim3 grid((out_w + NC_TX - 1) / NC_TX, (P.H + NC_TY - 1) / NC_TY,
-            (P.D + NC_DC - 1) / NC_DC);
-  const int r = P.r;
-  const size_t tile = (size_t)(NC_TY + 2 * r) * (NC_TX + 2 * r + NC_DC - 1);
-  const size_t lds = sizeof(float) * (2 * tile + (size_t)NC_DC * NC_TY * (NC_TX + 2 * r));
   if (P.p.dtype == STEREO_U8)
-    hipLaunchKernelGGL(ncc_kernel<uint8_t>, grid, dim3(256), lds, s,
-                       (const uint8_t*)ref, P.p.pitch_ref, tar_w, P.W, P.H, P.D, r,
-                       muX, isdX, muY, isdY, C, out_w, out_pitch, out_slice, anchor);
-  else
-    hipLaunchKernelGGL(ncc_kernel<float>, grid, dim3(256), lds, s,
-                       (const float*)ref, P.p.pitch_ref, tar_w, P.W, P.H, P.D, r,
-                       muX, isdX, muY, isdY, C, out_w, out_pitch, out_slice, anchor);
-  return hipGetLastError();
+    return launch_ncc_t(P, (const uint8_t*)ref, tar_w, muX, isdX, muY, isdY, C, out_w,
+                        out_pitch, out_slice, anchor, s);
+  return launch_ncc_t(P, (const float*)ref, tar_w, muX, isdX, muY, isdY, C, out_w, out_pitch,
+                      out_slice, anchor, s);
 }
 
 }  // namespace stereo

@@ -109,6 +109,23 @@ def test_workspace_checks(lib):
     lib.stereo_plan_destroy(h)
 
 
+def test_tuning_keys(lib):
+    p = make_params(64, 48, 16, delta_p=8, plane=(4, 0, 0.1))
+    s, h = _create(lib, p)
+    v = ctypes.c_int32()
+    assert lib.stereo_plan_get_tuning(h, b"agg_levels_u8", ctypes.byref(v)) == 0 and v.value == 8
+    assert lib.stereo_plan_set_tuning(h, b"agg_levels_f32", 16) == 0
+    assert lib.stereo_plan_get_tuning(h, b"agg_levels_f32", ctypes.byref(v)) == 0 and v.value == 16
+    assert lib.stereo_plan_set_tuning(h, b"agg_levels_f32", 12) == 1
+    assert lib.stereo_plan_set_tuning(h, b"no_such_key", 8) == 1
+    lib.stereo_plan_destroy(h)
+
+
+def test_volume_size_limit(lib):
+    p = make_params(8192, 8192, 256, delta_p=8, plane=(4, 0, 0.1))
+    assert _create(lib, p)[0] == 2
+
+
 def test_status_strings(lib):
     for k, v in _lib.STATUS.items():
         assert lib.stereo_status_string(k).decode() == v

@@ -149,6 +149,23 @@ def _check_selection(w, ora, dR, dT, dsub, valid, disp):
     PR.assert_subpixel_close(disp, np.where(both, ora["disp"], 0.0), both, curv, "disp")
 
 
+@pytest.mark.parametrize("name", ["c1", "rolled", "f32"])
+def test_tuning_variants_are_bitwise_identical(name):
+    """Launch-shape choices never change results: every level chunk gives the
+    same bits (fixed tap order per pixel, levels scanned in order)."""
+    w, sc, ora = case(name)
+    ref, tar = _dev(sc.ref), _dev(sc.tar)
+    outs = []
+    for lv in (8, 16):
+        plan = api.Plan.from_workload(w)
+        plan.set_tuning("agg_levels_u8", lv)
+        plan.set_tuning("agg_levels_f32", lv)
+        o = api.match(plan, ref, tar, want_target=True)
+        outs.append({k: _host(v) for k, v in o.items()})
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k], equal_nan=True), k
+
+
 def test_near_ties_are_rare():
     """The tie exception must stay an exception on textured scenes.  Exact
     ties are structural near the left border, where every level beyond
