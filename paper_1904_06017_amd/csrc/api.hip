@@ -127,7 +127,7 @@ stereo_status check_ws(const Plan& P, void* ws, size_t bytes) {
 
 // Statistics maps inside the workspace.
 struct StatMaps {
-  float *muX, *isdX, *muY, *isdY;
+  float *zX, *isdX, *zY, *isdY;
 };
 StatMaps stat_maps(const Plan& P, void* ws) {
   float* b = at<float>(ws, P.off_stats);
@@ -225,15 +225,15 @@ stereo_status stereo_cost_volume(stereo_plan_t plan, const void* ref, const floa
   stereo_status s = check_ws(P, ws, ws_bytes);
   if (s != STEREO_OK) return s;
   StatMaps m = stat_maps(P, ws);
-  STEREO_HIP(launch_block_stats(P, ref, P.p.dtype, P.p.pitch_ref, m.muX, m.isdX, stream),
+  STEREO_HIP(launch_block_stats(P, ref, P.p.dtype, P.p.pitch_ref, m.zX, m.isdX, stream),
              "block statistics (ref)");
-  STEREO_HIP(launch_block_stats(P, tar_w, STEREO_F32, P.W, m.muY, m.isdY, stream),
+  STEREO_HIP(launch_block_stats(P, tar_w, STEREO_F32, P.W, m.zY, m.isdY, stream),
              "block statistics (tar_w)");
   const int64_t slice = (int64_t)P.W * P.H;
-  STEREO_HIP(launch_ncc(P, ref, tar_w, m.muX, m.isdX, m.muY, m.isdY, cost_R, P.W, P.W, slice,
+  STEREO_HIP(launch_ncc(P, ref, tar_w, m.zX, m.isdX, m.zY, m.isdY, cost_R, P.W, P.W, slice,
                         0, stream), "ncc (reference volume)");
   if (cost_T)
-    STEREO_HIP(launch_ncc(P, ref, tar_w, m.muX, m.isdX, m.muY, m.isdY, cost_T, P.W, P.W, slice,
+    STEREO_HIP(launch_ncc(P, ref, tar_w, m.zX, m.isdX, m.zY, m.isdY, cost_T, P.W, P.W, slice,
                           1, stream), "ncc (target volume)");
   return STEREO_OK;
 }
@@ -306,16 +306,16 @@ stereo_status stereo_match_profiled(stereo_plan_t plan, const void* ref, const v
   STEREO_HIP(mark(0), "event record");
   STEREO_HIP(launch_warp(P, tar, tarw, stream), "warp");
   STEREO_HIP(mark(1), "event record");
-  STEREO_HIP(launch_block_stats(P, ref, P.p.dtype, P.p.pitch_ref, m.muX, m.isdX, stream),
+  STEREO_HIP(launch_block_stats(P, ref, P.p.dtype, P.p.pitch_ref, m.zX, m.isdX, stream),
              "block statistics (ref)");
-  STEREO_HIP(launch_block_stats(P, tarw, STEREO_F32, P.W, m.muY, m.isdY, stream),
+  STEREO_HIP(launch_block_stats(P, tarw, STEREO_F32, P.W, m.zY, m.isdY, stream),
              "block statistics (tar_w)");
   STEREO_HIP(mark(2), "event record");
   // One reference-anchored volume over the extended columns [0, W + D - 1):
   // the target volume is its re-indexing C_T(x, d) = C_R(x + d, d).
   const int64_t slice = (int64_t)P.H * P.cw;
   const int ext_w = P.W + P.D - 1;
-  STEREO_HIP(launch_ncc(P, ref, tarw, m.muX, m.isdX, m.muY, m.isdY, cvol, ext_w, P.cw, slice,
+  STEREO_HIP(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, cvol, ext_w, P.cw, slice,
                         0, stream), "ncc");
   STEREO_HIP(mark(3), "event record");
   BilArgs a{};

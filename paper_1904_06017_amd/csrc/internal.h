@@ -49,17 +49,18 @@ Consts consts_of(const Plan& P);
 hipError_t launch_warp(const Plan& P, const void* tar, float* tar_w,
                        hipStream_t s);
 
-// mu / 1/sigma of (I - 128) over the clamped (2r+1)^2 block centred at every
-// column x in [-r, W + r) and row y; isd = 0 marks a flat block.
+// z = mu / sigma and isd = 1 / sigma of (I - 128) over the clamped (2r+1)^2
+// block centred at every column x in [-r, W + r) and row y; a flat block
+// stores z = isd = 0.
 hipError_t launch_block_stats(const Plan& P, const void* img, stereo_dtype dt,
-                              int64_t pitch, float* mu, float* isd,
+                              int64_t pitch, float* z, float* isd,
                               hipStream_t s);
 
 // C[d][y][x], x in [0, out_w): anchor 0 compares the ref block at x with the
 // tar_w block at x - d; anchor 1 the ref block at x + d with tar_w at x.
-// ref statistics in (muX, isdX), tar_w statistics in (muY, isdY).
+// ref statistics in (zX, isdX), tar_w statistics in (zY, isdY).
 hipError_t launch_ncc(const Plan& P, const void* ref, const float* tar_w,
-                      const float* muX, const float* isdX, const float* muY,
+                      const float* zX, const float* isdX, const float* zY,
                       const float* isdY, float* C, int out_w, int64_t out_pitch,
                       int64_t out_slice, int anchor, hipStream_t s);
 

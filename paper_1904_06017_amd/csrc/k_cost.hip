@@ -49,13 +49,16 @@ warp_kernel(const T* __restrict__ tar, int64_t pitch, int W, int H,
 // Block statistics.  One workgroup covers 64 block centres x 16 rows; the
 // clamped input tile (16 + 2r rows x 64 + 2r columns, offset by -128) is
 // staged in LDS, then each thread forms the mean and the population
-// deviation of its blocks in two passes (mean first, then squared deviations).
+// deviation of its blocks in two passes (mean first, then squared
+// deviations).  Stored as z = mu / sigma and isd = 1 / sigma, so that the
+// cost is 1 + zX zY - (S / n) isdX isdY; a flat block stores z = isd = 0,
+// which makes its cost exactly 1 without a branch.
 constexpr int ST_TX = 64, ST_TY = 16;
 
 template <typename T>
 __global__ void __launch_bounds__(256)
 block_stats_kernel(const T* __restrict__ img, int64_t pitch, int W, int H, int r,
-                   float* __restrict__ mu, float* __restrict__ isd) {
+                   float* __restrict__ zmap, float* __restrict__ isd) {
   extern __shared__ float tile[];   // (ST_TY + 2r) x (ST_TX + 2r)
   const int SW = W + 2 * r;
   const int tw = ST_TX + 2 * r, th = ST_TY + 2 * r;
@@ -86,19 +89,21 @@ block_stats_kernel(const T* __restrict__ img, int64_t pitch, int W, int H, int r
         q = fmaf(e, e, q);
       }
     const float var = q * inv_n;
-    mu[(int64_t)y * SW + xi] = m;
-    isd[(int64_t)y * SW + xi] = (var < kFlatVar) ? 0.0f : 1.0f / sqrtf(var);
+    const float is = (var < kFlatVar) ? 0.0f : 1.0f / sqrtf(var);
+    zmap[(int64_t)y * SW + xi] = m * is;
+    isd[(int64_t)y * SW + xi] = is;
   }
 }
 
 // NCC cost, Eq. (8), in its equivalent 1 - NCC form on offset intensities:
-//   C = 1 - (S/n - muX muY) / (sdX sdY),  S = sum over the block of X' Y'.
-// A workgroup covers NC_TX = 64 output columns (one per lane) x NC_TY rows x
-// NC_DC levels (NC_DW per wave).  Each lane walks down its column: for every
-// input row it forms the horizontal sum of the 2r+1 products (fixed order
-// j = -r..r) and keeps the last 2r+1 row sums in a register ring; the block
-// sum is the fixed-order sum of that ring (i = -r..r).  So every output is
-// the same expression whatever the tiling.
+//   C = 1 - (S/n - muX muY) / (sdX sdY) = 1 + zX zY - (S/n) isdX isdY,
+// S = sum over the block of X' Y', z = mu / sd, isd = 1 / sd.
+// A workgroup covers NC_TX = 64 output columns (one per lane, conflict-free
+// LDS rows) x NC_TY rows x NC_DC levels (NC_DW per wave).  Each lane walks
+// down its column: for every input row it forms the horizontal sum of the
+// 2r+1 products (fixed order j = -r..r) and keeps the last 2r+1 row sums in a
+// register ring; the block sum is the fixed-order sum of that ring
+// (i = -r..r).  Every output is the same expression whatever the tiling.
 //
 // The unshifted operand A (X' for anchor 0, Y' for anchor 1) and the
 // level-shifted operand B are staged in LDS with clamped reads.
@@ -117,8 +122,8 @@ template <int r, typename T>
 __global__ void __launch_bounds__(256)
 ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
            const float* __restrict__ tarw, int W, int H, int D,
-           const float* __restrict__ muX, const float* __restrict__ isdX,
-           const float* __restrict__ muY, const float* __restrict__ isdY,
+           const float* __restrict__ zX, const float* __restrict__ isdX,
+           const float* __restrict__ zY, const float* __restrict__ isdY,
            float* __restrict__ C, int out_w, int64_t out_pitch,
            int64_t out_slice, int anchor) {
   using G = NccGeom<r>;
@@ -164,6 +169,7 @@ ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
   for (int k = 0; k < NC_DW; ++k)
 #pragma unroll
     for (int i = 0; i < K; ++i) ring[k][i] = 0.0f;
+  const int cx = min(x, W - 1 + r) + r;       // centre of the A block in the maps
 
   for (int yb = 0; yb < G::ROWS; yb += K) {
 #pragma unroll
@@ -183,6 +189,9 @@ ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
         }
         const int y = y0 + yy - 2 * r;        // output row completed by this input row
         if (yy >= 2 * r && y < H && x < out_w) {
+          const int64_t rowo = (int64_t)y * SW;
+          const float zA = anchor ? zY[rowo + cx] : zX[rowo + cx];
+          const float iA = (anchor ? isdY[rowo + cx] : isdX[rowo + cx]) * inv_n;
 #pragma unroll
           for (int k = 0; k < NC_DW; ++k) {
             const int d = d0 + wave * NC_DW + k;
@@ -191,16 +200,10 @@ ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
             float S = ring[k][(s + 1) % K];
 #pragma unroll
             for (int i = 2; i <= K; ++i) S += ring[k][(s + i) % K];
-            const int cxX = min(max(anchor ? x + d : x, -r), W - 1 + r) + r;
-            const int cxY = min(max(anchor ? x : x - d, -r), W - 1 + r) + r;
-            const int64_t rowo = (int64_t)y * SW;
-            const float ix = isdX[rowo + cxX];
-            const float iy = isdY[rowo + cxY];
-            float c = 1.0f;
-            if (ix != 0.0f && iy != 0.0f) {
-              const float cov = fmaf(S, inv_n, -muX[rowo + cxX] * muY[rowo + cxY]);
-              c = 1.0f - cov * ix * iy;
-            }
+            const int cb = min(max(anchor ? x + d : x - d, -r), W - 1 + r) + r;
+            const float zB = anchor ? zX[rowo + cb] : zY[rowo + cb];
+            const float iB = anchor ? isdX[rowo + cb] : isdY[rowo + cb];
+            const float c = fmaf(-S * iA, iB, fmaf(zA, zB, 1.0f));
             C[(int64_t)d * out_slice + (int64_t)y * out_pitch + x] = c;
           }
         }
@@ -210,25 +213,25 @@ ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
 }
 
 template <int r, typename T>
-hipError_t launch_ncc_r(const Plan& P, const T* ref, const float* tar_w, const float* muX,
-                        const float* isdX, const float* muY, const float* isdY, float* C,
+hipError_t launch_ncc_r(const Plan& P, const T* ref, const float* tar_w, const float* zX,
+                        const float* isdX, const float* zY, const float* isdY, float* C,
                         int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
                         hipStream_t s) {
   dim3 grid((out_w + NC_TX - 1) / NC_TX, (P.H + NC_TY - 1) / NC_TY,
             (P.D + NC_DC - 1) / NC_DC);
   hipLaunchKernelGGL((ncc_kernel<r, T>), grid, dim3(256), NccGeom<r>::lds_bytes, s, ref,
-                     P.p.pitch_ref, tar_w, P.W, P.H, P.D, muX, isdX, muY, isdY, C, out_w,
+                     P.p.pitch_ref, tar_w, P.W, P.H, P.D, zX, isdX, zY, isdY, C, out_w,
                      out_pitch, out_slice, anchor);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_ncc_t(const Plan& P, const T* ref, const float* tar_w, const float* muX,
-                        const float* isdX, const float* muY, const float* isdY, float* C,
+hipError_t launch_ncc_t(const Plan& P, const T* ref, const float* tar_w, const float* zX,
+                        const float* isdX, const float* zY, const float* isdY, float* C,
                         int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
                         hipStream_t s) {
 #define NCC_CASE(R_) \
-  case R_: return launch_ncc_r<R_, T>(P, ref, tar_w, muX, isdX, muY, isdY, C, out_w, \
+  case R_: return launch_ncc_r<R_, T>(P, ref, tar_w, zX, isdX, zY, isdY, C, out_w, \
                                       out_pitch, out_slice, anchor, s);
   switch (P.r) {
     NCC_CASE(1) NCC_CASE(2) NCC_CASE(3) NCC_CASE(4)
@@ -256,27 +259,27 @@ hipError_t launch_warp(const Plan& P, const void* tar, float* tar_w, hipStream_t
 }
 
 hipError_t launch_block_stats(const Plan& P, const void* img, stereo_dtype dt,
-                              int64_t pitch, float* mu, float* isd, hipStream_t s) {
+                              int64_t pitch, float* z, float* isd, hipStream_t s) {
   const int SW = P.W + 2 * P.r;
   dim3 grid((SW + ST_TX - 1) / ST_TX, (P.H + ST_TY - 1) / ST_TY);
   const size_t lds = sizeof(float) * (ST_TX + 2 * P.r) * (ST_TY + 2 * P.r);
   if (dt == STEREO_U8)
     hipLaunchKernelGGL(block_stats_kernel<uint8_t>, grid, dim3(256), lds, s,
-                       (const uint8_t*)img, pitch, P.W, P.H, P.r, mu, isd);
+                       (const uint8_t*)img, pitch, P.W, P.H, P.r, z, isd);
   else
     hipLaunchKernelGGL(block_stats_kernel<float>, grid, dim3(256), lds, s,
-                       (const float*)img, pitch, P.W, P.H, P.r, mu, isd);
+                       (const float*)img, pitch, P.W, P.H, P.r, z, isd);
   return hipGetLastError();
 }
 
 hipError_t launch_ncc(const Plan& P, const void* ref, const float* tar_w,
-                      const float* muX, const float* isdX, const float* muY,
+                      const float* zX, const float* isdX, const float* zY,
                       const float* isdY, float* C, int out_w, int64_t out_pitch,
                       int64_t out_slice, int anchor, hipStream_t s) {
   if (P.p.dtype == STEREO_U8)
-    return launch_ncc_t(P, (const uint8_t*)ref, tar_w, muX, isdX, muY, isdY, C, out_w,
+    return launch_ncc_t(P, (const uint8_t*)ref, tar_w, zX, isdX, zY, isdY, C, out_w,
                         out_pitch, out_slice, anchor, s);
-  return launch_ncc_t(P, (const float*)ref, tar_w, muX, isdX, muY, isdY, C, out_w, out_pitch,
+  return launch_ncc_t(P, (const float*)ref, tar_w, zX, isdX, zY, isdY, C, out_w, out_pitch,
                       out_slice, anchor, s);
 }
 

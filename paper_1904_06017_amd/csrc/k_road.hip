@@ -10,8 +10,8 @@
 //   E(psi) = Sdd - alpha . b                                       (Eq. 23)
 //   dE/dpsi = -2 alpha1 (Sdy' - alpha0 Sy' - alpha1 Syy')          (Eq. 26)
 // The sums are accumulated in FP64 in a fixed order (per-thread grid-stride
-// sums, a fixed tree per block, then blocks in index order), so the fit is
-// deterministic.
+// sums, a fixed tree per block, then a fixed tree over the block partials),
+// so the fit is deterministic.
 #include "internal.h"
 
 namespace stereo {
@@ -59,8 +59,7 @@ struct Fit {
   double a0, a1, sdy, sy;
 };
 
-__device__ Fit alpha_at(const Mom& m, double psi) {
-  const double c = cos(psi), s = sin(psi);
+__device__ Fit alpha_cs(const Mom& m, double c, double s) {
   Fit f;
   f.sy = c * m.sv - s * m.su;
   const double syy = c * c * m.svv - 2.0 * s * c * m.suv + s * s * m.suu;
@@ -71,14 +70,21 @@ __device__ Fit alpha_at(const Mom& m, double psi) {
   return f;
 }
 
+__device__ Fit alpha_at(const Mom& m, double psi) {
+  double s, c;
+  sincos(psi, &s, &c);
+  return alpha_cs(m, c, s);
+}
+
 __device__ double energy_at(const Mom& m, double psi) {
   const Fit f = alpha_at(m, psi);
   return m.sdd - (f.a0 * m.sd + f.a1 * f.sdy);
 }
 
 __device__ double gradient_at(const Mom& m, double psi) {
-  const double c = cos(psi), s = sin(psi);
-  const Fit f = alpha_at(m, psi);
+  double s, c;
+  sincos(psi, &s, &c);
+  const Fit f = alpha_cs(m, c, s);
   const double syp = -s * m.sv - c * m.su;
   const double syyp = s * c * (m.suu - m.svv) + (s * s - c * c) * m.suv;
   const double sdyp = -s * m.sdv - c * m.sdu;
@@ -92,22 +98,37 @@ __device__ double wrap_half_pi(double psi) {
   return w - pi / 2.0;
 }
 
-// One wave: sum the block partials in index order, then one lane runs the
-// descent.  Rate: Eq. (28), lambda_k+1 = lambda_k g_k / (g_k - g_k+1); a step
-// is halved while it raises the normalised energy or exceeds pi/4; a
-// non-positive rate restarts at lambda0.
-__global__ void __launch_bounds__(64)
+// One block: thread b loads the partial sums of block b, then a fixed tree
+// combines them (deterministic); one lane then runs the descent.  Rate:
+// Eq. (28), lambda_k+1 = lambda_k g_k / (g_k - g_k+1); a step is halved while
+// it raises the normalised energy or exceeds pi/4; a non-positive rate
+// restarts at lambda0.
+__global__ void __launch_bounds__(kRoadThreads)
 road_fit_kernel(const double* __restrict__ partials, int nblocks, int W, int H,
                 double psi0, double lambda0, double delta_psi, int max_iter,
                 stereo_road_fit* __restrict__ out) {
-  __shared__ double mom[kMom];
-  if (threadIdx.x < kMom) {
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partials[(int64_t)b * kMom + threadIdx.x];
-    mom[threadIdx.x] = s;
+  __shared__ double red[kMom][kRoadThreads];
+  double a[kMom];
+#pragma unroll
+  for (int j = 0; j < kMom; ++j) a[j] = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kRoadThreads) {
+#pragma unroll
+    for (int j = 0; j < kMom; ++j) a[j] += partials[(int64_t)b * kMom + j];
   }
+#pragma unroll
+  for (int j = 0; j < kMom; ++j) red[j][threadIdx.x] = a[j];
   __syncthreads();
+  for (int s = kRoadThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+#pragma unroll
+      for (int j = 0; j < kMom; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
   if (threadIdx.x != 0) return;
+  double mom[kMom];
+#pragma unroll
+  for (int j = 0; j < kMom; ++j) mom[j] = red[j][0];
   Mom m{mom[0], mom[1], mom[2], mom[3], mom[4], mom[5], mom[6], mom[7], mom[8], mom[9]};
   stereo_road_fit r;
   r.n_points = m.n;
@@ -193,7 +214,7 @@ hipError_t launch_road(const Plan& P, const float* disp, const uint8_t* mask,
                      disp, mask, P.W, P.H, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(road_fit_kernel, dim3(1), dim3(64), 0, s, partials, P.road_blocks,
+  hipLaunchKernelGGL(road_fit_kernel, dim3(1), dim3(kRoadThreads), 0, s, partials, P.road_blocks,
                      P.W, P.H, psi0, lambda0, delta_psi, max_iter, fit);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
