@@ -108,9 +108,13 @@ stereo_status stereo_plan_workspace_bytes(stereo_plan_t plan, size_t* bytes);
 stereo_status stereo_plan_get_params(stereo_plan_t plan, stereo_params* out);
 
 /* ---- tuning knobs (host only) ---------------------------------------------
- * Launch-shape choices that never change results.  Keys:
+ * Launch-shape choices.  Keys:
  *   "agg_levels_u8", "agg_levels_f32": disparity levels staged per pass of
- *   the aggregation kernel for 8-bit / float guides, 8 or 16 (default 8).
+ *   the aggregation kernel for 8-bit / float guides, 8 or 16 (default 8);
+ *   results are bitwise identical for every value;
+ *   "grad_levels": levels recomputed per tile by stereo_backward, a multiple
+ *   of 4 in 4..64 (default 16); changes the workspace size and the FP32
+ *   summation order of the gradients (not their value beyond rounding).
  * Unknown keys and values give INVALID_ARGUMENT.  Not thread-safe against
  * concurrent enqueues on the same plan. */
 stereo_status stereo_plan_set_tuning(stereo_plan_t plan, const char* key, int32_t value);
@@ -198,6 +202,45 @@ stereo_status stereo_road_transform(stereo_plan_t plan, const float* disp,
                                     stereo_road_fit* fit_dev, float* disp_t,
                                     void* ws, size_t ws_bytes,
                                     hipStream_t stream);
+
+/* ---- differentiable form (F32 plans, perspective = 1) --------------------
+ * Soft-argmin head over the aggregated reference volume E_R (Eqs. 8-11):
+ *   P(p,d) = softmax_d(-E_R(p,d) / T),  dh(p) = sum_d d P(p,d),
+ *   disp_soft(p) = dh - delta_p + d_road(u - dh + delta_p, v).
+ * plane: host double[3], the road plane of the warp and of the shift back for
+ * this call (the parameter being learned; params.plane is not used).
+ * disp_soft: [H][W] FP32.  saved: [3][H][W] FP32 = (max_d(-E/T), log of the
+ * softmax normaliser, dh) -- everything the backward needs; the cost volume
+ * itself is not kept. */
+stereo_status stereo_soft_forward(stereo_plan_t plan, const float* ref, const float* tar,
+                                  const double plane[3], float* disp_soft, float* saved,
+                                  void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Vector-Jacobian product of disp_soft with grad_disp ([H][W] FP32): writes
+ * grad_ref, grad_tar ([H][W] FP32) and grad_plane (device double[3]).  The cost
+ * and aggregated volumes are recomputed per tile of "grad_levels" levels (a
+ * tuning key, default 16).  Gradients flow through the aggregation weights
+ * (guide = ref), the NCC cost of both images, the warp and the shift back.
+ * Deterministic: gathers in a fixed order, and fixed-point integer sums
+ * (scale 2^44) where the warp scatters into the target image, so per-pixel
+ * contributions must stay below 2^19 in magnitude. */
+stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float* tar,
+                              const double plane[3], const float* saved,
+                              const float* grad_disp, float* grad_ref, float* grad_tar,
+                              double* grad_plane, void* ws, size_t ws_bytes,
+                              hipStream_t stream);
+
+/* Photometric L1 loss L = mean_p |ref(p) - lerp(tar, v, u - disp_soft(p))|
+ * (row lerp, clamped), written to *loss_dev (device double).  The _bwd call
+ * writes dL/dref, dL/dtar, dL/ddisp times grad_loss (each nullable). */
+stereo_status stereo_photometric_l1(stereo_plan_t plan, const float* ref, const float* tar,
+                                    const float* disp_soft, double* loss_dev, void* ws,
+                                    size_t ws_bytes, hipStream_t stream);
+stereo_status stereo_photometric_l1_bwd(stereo_plan_t plan, const float* ref,
+                                        const float* tar, const float* disp_soft,
+                                        double grad_loss, float* g_ref, float* g_tar,
+                                        float* g_disp, void* ws, size_t ws_bytes,
+                                        hipStream_t stream);
 
 #ifdef __cplusplus
 }

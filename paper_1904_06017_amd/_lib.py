@@ -76,6 +76,16 @@ SIGNATURES = {
     "stereo_road_transform": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double,
                                       c_double, c_int32, c_float, c_void_p, c_void_p,
                                       c_void_p, c_size_t, c_void_p]),
+    "stereo_soft_forward": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_double), c_void_p,
+                                    c_void_p, c_void_p, c_size_t, c_void_p]),
+    "stereo_backward": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_double), c_void_p,
+                                c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                                c_void_p]),
+    "stereo_photometric_l1": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_size_t, c_void_p]),
+    "stereo_photometric_l1_bwd": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                                          c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                                          c_void_p]),
 }
 
 _lib = None

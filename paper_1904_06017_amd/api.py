@@ -107,7 +107,13 @@ class Plan:
         return torch.uint8 if self.params.dtype == _lib.U8 else torch.float32
 
     def set_tuning(self, key: str, value: int):
-        check(_lib.load().stereo_plan_set_tuning(self._h, key.encode(), int(value)))
+        lib = _lib.load()
+        check(lib.stereo_plan_set_tuning(self._h, key.encode(), int(value)))
+        n = ctypes.c_size_t()
+        check(lib.stereo_plan_workspace_bytes(self._h, ctypes.byref(n)))
+        if int(n.value) != self.workspace_bytes:
+            self.workspace_bytes = int(n.value)
+            self._ws = None
 
     def get_tuning(self, key: str) -> int:
         v = ctypes.c_int32()
@@ -226,3 +232,61 @@ def road_transform(plan: Plan, disp, mask=None, psi_init=0.0, lambda0=LAMBDA0,
         int(max_iter), float(delta_t), _p(fit_buf), _p(out), _p(ws), plan.workspace_bytes,
         _stream()))
     return (road_fit_from_bytes(fit_buf) if read_fit else fit_buf), out
+
+
+# ---- differentiable form ----------------------------------------------------
+def _plane3(plane):
+    vals = [float(x) for x in (plane.detach().cpu().tolist() if isinstance(plane, torch.Tensor)
+                               else plane)]
+    if len(vals) != 3:
+        raise ValueError("plane must have 3 entries")
+    return (ctypes.c_double * 3)(*vals)
+
+
+def soft_forward(plan: Plan, ref, tar, plane):
+    """Soft-argmin disparity; returns (disp_soft [H][W], saved [3][H][W])."""
+    _need(ref, torch.float32, (plan.H, plan.W), "ref")
+    _need(tar, torch.float32, (plan.H, plan.W), "tar")
+    disp = torch.empty((plan.H, plan.W), dtype=torch.float32, device=ref.device)
+    saved = torch.empty((3, plan.H, plan.W), dtype=torch.float32, device=ref.device)
+    ws = plan.workspace(ref.device)
+    check(_lib.load().stereo_soft_forward(plan.handle, _p(ref), _p(tar), _plane3(plane), _p(disp),
+                                          _p(saved), _p(ws), plan.workspace_bytes, _stream()))
+    return disp, saved
+
+
+def backward(plan: Plan, ref, tar, plane, saved, grad_disp):
+    """VJP of soft_forward: returns (grad_ref, grad_tar, grad_plane[3] float64)."""
+    _need(saved, torch.float32, (3, plan.H, plan.W), "saved")
+    _need(grad_disp, torch.float32, (plan.H, plan.W), "grad_disp")
+    dev = ref.device
+    g_ref = torch.empty((plan.H, plan.W), dtype=torch.float32, device=dev)
+    g_tar = torch.empty((plan.H, plan.W), dtype=torch.float32, device=dev)
+    g_plane = torch.empty(3, dtype=torch.float64, device=dev)
+    ws = plan.workspace(dev)
+    check(_lib.load().stereo_backward(plan.handle, _p(ref), _p(tar), _plane3(plane), _p(saved),
+                                      _p(grad_disp), _p(g_ref), _p(g_tar), _p(g_plane), _p(ws),
+                                      plan.workspace_bytes, _stream()))
+    return g_ref, g_tar, g_plane
+
+
+def photometric_l1(plan: Plan, ref, tar, disp):
+    _need(disp, torch.float32, (plan.H, plan.W), "disp")
+    loss = torch.empty((), dtype=torch.float64, device=ref.device)
+    ws = plan.workspace(ref.device)
+    check(_lib.load().stereo_photometric_l1(plan.handle, _p(ref), _p(tar), _p(disp), _p(loss),
+                                            _p(ws), plan.workspace_bytes, _stream()))
+    return loss
+
+
+def photometric_l1_bwd(plan: Plan, ref, tar, disp, grad_loss=1.0):
+    dev = ref.device
+    g_ref = torch.empty((plan.H, plan.W), dtype=torch.float32, device=dev)
+    g_tar = torch.empty((plan.H, plan.W), dtype=torch.float32, device=dev)
+    g_disp = torch.empty((plan.H, plan.W), dtype=torch.float32, device=dev)
+    ws = plan.workspace(dev)
+    check(_lib.load().stereo_photometric_l1_bwd(plan.handle, _p(ref), _p(tar), _p(disp),
+                                                float(grad_loss), _p(g_ref), _p(g_tar),
+                                                _p(g_disp), _p(ws), plan.workspace_bytes,
+                                                _stream()))
+    return g_ref, g_tar, g_disp

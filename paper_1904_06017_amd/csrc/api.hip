@@ -40,10 +40,6 @@ Consts consts_of(const Plan& P) {
 
 using namespace stereo;
 
-struct stereo_plan_s {
-  Plan P;
-};
-
 namespace {
 
 stereo_status validate(const stereo_params* p) {
@@ -102,7 +98,7 @@ void layout(Plan& P) {
   P.off_dT = o;    o = align256(o + sizeof(int16_t) * (size_t)W * H);
   P.off_dsub = o;  o = align256(o + sizeof(float) * (size_t)W * H);
   P.off_road = o;  o = align256(o + sizeof(double) * 10 * (size_t)P.road_blocks);
-  P.ws_bytes = o;
+  P.ws_bytes = grad_layout(P, o);
 }
 
 template <typename T>
@@ -188,6 +184,14 @@ stereo_status stereo_plan_workspace_bytes(stereo_plan_t plan, size_t* bytes) {
 stereo_status stereo_plan_set_tuning(stereo_plan_t plan, const char* key, int32_t value) {
   STEREO_REQUIRE(plan && key, "plan and key must be non-NULL");
   const std::string k(key);
+  if (k == "grad_levels") {
+    STEREO_REQUIRE(value >= 4 && value <= 64 && value % 4 == 0,
+                   "grad_levels must be a multiple of 4 in 4..64");
+    plan->P.grad_levels = value;
+    plan->P.ws_bytes = grad_layout(plan->P, plan->P.off_road +
+                                   align256(sizeof(double) * 10 * (size_t)plan->P.road_blocks));
+    return STEREO_OK;
+  }
   if (k == "agg_levels_u8" || k == "agg_levels_f32") {
     STEREO_REQUIRE(value == 8 || value == 16, "%s must be 8 or 16", key);
     (k == "agg_levels_u8" ? plan->P.agg_levels_u8 : plan->P.agg_levels_f32) = value;
@@ -201,6 +205,7 @@ stereo_status stereo_plan_get_tuning(stereo_plan_t plan, const char* key, int32_
   const std::string k(key);
   if (k == "agg_levels_u8") { *value = plan->P.agg_levels_u8; return STEREO_OK; }
   if (k == "agg_levels_f32") { *value = plan->P.agg_levels_f32; return STEREO_OK; }
+  if (k == "grad_levels") { *value = plan->P.grad_levels; return STEREO_OK; }
   return fail(STEREO_ERR_INVALID_ARGUMENT, "unknown tuning key '%s'", key);
 }
 

@@ -36,6 +36,22 @@ struct Plan {
   // tuning (stereo_plan_set_tuning): levels per aggregation pass by guide type
   int agg_levels_u8 = 8;
   int agg_levels_f32 = 8;
+  // differentiable form (F32 plans): levels recomputed per backward tile and
+  // the workspace regions it uses (offsets from the workspace base)
+  int grad_levels = 16;
+  size_t g_off[32];
+  size_t g_end;
+};
+
+// Workspace regions of the backward (indices into Plan::g_off).
+enum GradRegion {
+  GR_WP, GR_AP, GR_A1, GR_A2,
+  GR_SUMS,                                      // [3][H][W]: alpha muY, beta, beta muX
+  GR_GX, GR_GTARW,
+  GR_CT, GR_ET, GR_GET, GR_GT, GR_GCT, GR_FA,   // GR_FA: [4][DT][H][W] alpha maps
+  GR_BA,                                        // [4][DT][HV][WVX] boxes
+  GR_BS,                                        // [3][HV][WVX] boxes of the sums
+  GR_GXV, GR_GYV, GR_GTARFIX, GR_PART_A, GR_PART_B, GR_SCRATCH, GR_COUNT
 };
 
 // Float view of a few plan parameters, precomputed on the host.
@@ -59,10 +75,12 @@ hipError_t launch_block_stats(const Plan& P, const void* img, stereo_dtype dt,
 // C[d][y][x], x in [0, out_w): anchor 0 compares the ref block at x with the
 // tar_w block at x - d; anchor 1 the ref block at x + d with tar_w at x.
 // ref statistics in (zX, isdX), tar_w statistics in (zY, isdY).
+// Levels [d_first, d_end) (d_end < 0: all D), written to slice d - d_first.
 hipError_t launch_ncc(const Plan& P, const void* ref, const float* tar_w,
                       const float* zX, const float* isdX, const float* zY,
                       const float* isdY, float* C, int out_w, int64_t out_pitch,
-                      int64_t out_slice, int anchor, hipStream_t s);
+                      int64_t out_slice, int anchor, hipStream_t s, int d_first = 0,
+                      int d_end = -1);
 
 struct BilArgs {
   const float* C;     // cost slices: C[d * c_slice + y * c_pitch + x + d*shift]
@@ -72,12 +90,20 @@ struct BilArgs {
   const void* guide;  // guide image
   stereo_dtype guide_dt;
   int64_t guide_pitch;
-  float* E;           // mode 0: aggregated volume [D][H][W]
+  float* E;           // modes 0, 4: output volume [levels][H][W]
   int16_t* dint;      // mode 1: WTA level [H][W]
   float* dsub;        // mode 1: sub-pixel level [H][W] (nullable)
+  float* sm_m;        // mode 2: softmax state and outputs [H][W]
+  float* sm_logZ;
+  float* sm_dh;
+  float* disp;
+  double plane[3];    // mode 2: plane of the shift back
+  int levels;         // number of levels in C (0: plan D)
 };
 // mode 0: write the normalised aggregated volume; mode 1: fused WTA and
-// sub-pixel refinement (the volume never leaves the chip).
+// sub-pixel refinement (the volume never leaves the chip); mode 2: fused
+// soft-argmin (soft level, softmax state, shifted disparity); mode 4: the
+// unnormalised weighted sum sum_q w(p, q) C(q, d) (adjoint gather).
 hipError_t launch_bilateral(const Plan& P, const BilArgs& a, int mode,
                             hipStream_t s);
 
@@ -87,9 +113,17 @@ hipError_t launch_lr_check(const Plan& P, const int16_t* dR, const int16_t* dT,
                            const float* dsub, uint8_t* valid, float* disp,
                            hipStream_t s);
 
+// Grad workspace layout for the plan (sets g_off / g_end); 0 for U8 plans.
+size_t grad_layout(Plan& P, size_t base);
+
 hipError_t launch_road(const Plan& P, const float* disp, const uint8_t* mask,
                        double psi0, double lambda0, double delta_psi,
                        int max_iter, float delta_t, stereo_road_fit* fit,
                        float* disp_t, double* partials, hipStream_t s);
 
 }  // namespace stereo
+
+// The opaque plan handle of the C ABI.
+struct stereo_plan_s {
+  stereo::Plan P;
+};

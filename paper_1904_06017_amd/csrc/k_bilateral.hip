@@ -65,6 +65,19 @@ struct BilGeom {
   }
 };
 
+// Outputs and epilogue constants of one launch.
+struct BilOut {
+  float* E;                         // modes 0, 4
+  int16_t* dint;                    // mode 1
+  float* dsub;                      // mode 1 (nullable)
+  float* sm_m;                      // mode 2: max_d(-E/T)
+  float* sm_logZ;                   // mode 2: log sum_d exp(-E/T - m)
+  float* sm_dh;                     // mode 2: soft level
+  float* disp;                      // mode 2: shifted back
+  float invT;
+  double delta_p, c0, c1, c2;
+};
+
 template <typename G>
 __device__ __forceinline__ float guide_at(const G* g, int64_t pitch, int x, int y) {
   return static_cast<float>(g[(int64_t)y * pitch + x]);
@@ -74,9 +87,7 @@ template <int R, int PX, int DC, int TYT, typename GT, int MODE>
 __global__ void __launch_bounds__(kThreads)
 bilateral_kernel(const float* __restrict__ C, int64_t c_slice, int64_t c_pitch,
                  int shift, const GT* __restrict__ guide, int64_t g_pitch,
-                 int W, int H, int D, float ks2, float kr2,
-                 float* __restrict__ E, int16_t* __restrict__ dint,
-                 float* __restrict__ dsub) {
+                 int W, int H, int D, float ks2, float kr2, BilOut o) {
   using Gm = BilGeom<R, PX, DC, TYT>;
   constexpr bool TAB = std::is_same<GT, uint8_t>::value;
   extern __shared__ float4 lds4[];
@@ -135,6 +146,7 @@ bilateral_kernel(const float* __restrict__ C, int64_t c_slice, int64_t c_pitch,
 #pragma unroll
   for (int k = 0; k < PX; ++k) tp[k] = reinterpret_cast<const char*>(Tab) + gp4[k];
 
+  constexpr bool NORM = (MODE == 0 || MODE == 2);   // needs sum_q w(p, q)
   float wsum[PX];
   float rinv[PX];
 #pragma unroll
@@ -142,10 +154,15 @@ bilateral_kernel(const float* __restrict__ C, int64_t c_slice, int64_t c_pitch,
   // running winner-take-all state per pixel (mode 1)
   float bestE[PX], Em[PX], Ep[PX], prev[PX];
   int bestD[PX];
+  // running soft-argmin state per pixel (mode 2), base-2 exponents:
+  // m2 = max_d z, Z = sum_d 2^(z - m2), S1 = sum_d d 2^(z - m2), z = -E log2(e) / T
+  float m2[PX], Zs[PX], S1[PX];
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
     bestE[k] = 3.402823466e38f; Em[k] = 0.0f; Ep[k] = 0.0f; prev[k] = 0.0f; bestD[k] = 0;
+    m2[k] = -3.402823466e38f; Zs[k] = 0.0f; S1[k] = 0.0f;
   }
+  const float zscale = -o.invT * 1.4426950408889634f;
 
   // element step from level d to d + 1 (the target volume also moves one
   // column to the right per level)
@@ -218,7 +235,7 @@ bilateral_kernel(const float* __restrict__ C, int64_t c_slice, int64_t c_pitch,
           }
         }
       }
-      if (MODE == 0 && first) {
+      if (NORM && first) {
 #pragma unroll
         for (int k = 0; k < PX; ++k)
 #pragma unroll
@@ -243,7 +260,7 @@ bilateral_kernel(const float* __restrict__ C, int64_t c_slice, int64_t c_pitch,
       }
     }
 
-    if (MODE == 0 && first) {
+    if (NORM && first) {
 #pragma unroll
       for (int k = 0; k < PX; ++k) rinv[k] = 1.0f / wsum[k];
     }
@@ -252,12 +269,32 @@ bilateral_kernel(const float* __restrict__ C, int64_t c_slice, int64_t c_pitch,
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
       const int px = x0 + tx * PX + k;
-      if (MODE == 0) {
+      if (MODE == 0 || MODE == 4) {
+        // mode 0: normalised E (Eq. 11); mode 4: the weighted sum alone
         if (py < H && px < W) {
 #pragma unroll
           for (int j = 0; j < DC; ++j) {
             const int d = d0 + j;
-            if (d < D) E[((int64_t)d * H + py) * W + px] = acc[k][j] * rinv[k];
+            if (d < D) o.E[((int64_t)d * H + py) * W + px] = MODE == 0 ? acc[k][j] * rinv[k]
+                                                                       : acc[k][j];
+          }
+        }
+      } else if (MODE == 2) {
+#pragma unroll
+        for (int j = 0; j < DC; ++j) {
+          const int d = d0 + j;
+          if (d < D) {
+            const float z = acc[k][j] * rinv[k] * zscale;
+            if (z > m2[k]) {
+              const float sc = __builtin_amdgcn_exp2f(m2[k] - z);
+              Zs[k] = fmaf(Zs[k], sc, 1.0f);
+              S1[k] = fmaf(S1[k], sc, (float)d);
+              m2[k] = z;
+            } else {
+              const float e = __builtin_amdgcn_exp2f(z - m2[k]);
+              Zs[k] += e;
+              S1[k] = fmaf((float)d, e, S1[k]);
+            }
           }
         }
       } else {
@@ -279,6 +316,27 @@ bilateral_kernel(const float* __restrict__ C, int64_t c_slice, int64_t c_pitch,
     __syncthreads();
   }
 
+  if (MODE == 2) {
+    // soft level dh = sum_d d P(d), saved state (m, log Z) in natural units,
+    // and the shift back D = dh - delta_p + d_road(u - dh + delta_p, v)
+    const int py = y0 + ty;
+    const float ln2 = 0.6931471805599453f;
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+      const int px = x0 + tx * PX + k;
+      if (py < H && px < W) {
+        const int64_t pix = (int64_t)py * W + px;
+        const float dh = S1[k] / Zs[k];
+        o.sm_m[pix] = m2[k] * ln2;
+        o.sm_logZ[pix] = __builtin_amdgcn_logf(Zs[k]) * ln2;
+        o.sm_dh[pix] = dh;
+        const double dd = dh;
+        o.disp[pix] = (float)(dd - o.delta_p + (o.c0 + o.c1 * ((double)px - dd + o.delta_p) +
+                                                o.c2 * (double)py));
+      }
+    }
+  }
+
   if (MODE == 1) {
     const int py = y0 + ty;
 #pragma unroll
@@ -286,14 +344,14 @@ bilateral_kernel(const float* __restrict__ C, int64_t c_slice, int64_t c_pitch,
       const int px = x0 + tx * PX + k;
       if (py < H && px < W) {
         const int d = bestD[k];
-        dint[(int64_t)py * W + px] = (int16_t)d;
-        if (dsub) {
+        o.dint[(int64_t)py * W + px] = (int16_t)d;
+        if (o.dsub) {
           float off = 0.0f;
           if (d > 0 && d < D - 1) {
             const float den = 2.0f * Em[k] + 2.0f * Ep[k] - 4.0f * bestE[k];
             if (den > 0.0f) off = (Em[k] - Ep[k]) / den;
           }
-          dsub[(int64_t)py * W + px] = (float)d + off;
+          o.dsub[(int64_t)py * W + px] = (float)d + off;
         }
       }
     }
@@ -315,20 +373,34 @@ hipError_t launch_one(const Plan& P, const BilArgs& a, hipStream_t s) {
   }
   dim3 grid((P.W + Gm::TW - 1) / Gm::TW, (P.H + Gm::TH - 1) / Gm::TH);
   const Consts c = consts_of(P);
+  BilOut o;
+  o.E = a.E; o.dint = a.dint; o.dsub = a.dsub;
+  o.sm_m = a.sm_m; o.sm_logZ = a.sm_logZ; o.sm_dh = a.sm_dh; o.disp = a.disp;
+  o.invT = 1.0f / P.p.softargmin_T;
+  o.delta_p = P.p.perspective ? (double)P.p.delta_p : 0.0;
+  o.c0 = a.plane[0]; o.c1 = a.plane[1]; o.c2 = a.plane[2];
   hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, a.C, a.c_slice,
                      a.c_pitch, a.shift, (const GT*)a.guide, a.guide_pitch, P.W, P.H,
-                     P.D, c.ks2, c.kr2, a.E, a.dint, a.dsub);
+                     a.levels > 0 ? a.levels : P.D, c.ks2, c.kr2, o);
   return hipGetLastError();
+}
+
+template <int R, int DC, typename GT>
+hipError_t launch_rdg(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
+  constexpr int PX = 4, TYT = 32;
+  switch (mode) {
+    case 0: return launch_one<R, PX, DC, TYT, GT, 0>(P, a, s);
+    case 1: return launch_one<R, PX, DC, TYT, GT, 1>(P, a, s);
+    case 2: return launch_one<R, PX, DC, TYT, GT, 2>(P, a, s);
+    case 4: return launch_one<R, PX, DC, TYT, GT, 4>(P, a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int R, int DC>
 hipError_t launch_rd(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
-  constexpr int PX = 4, TYT = 32;
-  if (a.guide_dt == STEREO_U8)
-    return mode == 0 ? launch_one<R, PX, DC, TYT, uint8_t, 0>(P, a, s)
-                     : launch_one<R, PX, DC, TYT, uint8_t, 1>(P, a, s);
-  return mode == 0 ? launch_one<R, PX, DC, TYT, float, 0>(P, a, s)
-                   : launch_one<R, PX, DC, TYT, float, 1>(P, a, s);
+  return a.guide_dt == STEREO_U8 ? launch_rdg<R, DC, uint8_t>(P, a, mode, s)
+                                 : launch_rdg<R, DC, float>(P, a, mode, s);
 }
 
 template <int R>

@@ -121,7 +121,7 @@ struct NccGeom {
 template <int r, typename T>
 __global__ void __launch_bounds__(256)
 ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
-           const float* __restrict__ tarw, int W, int H, int D,
+           const float* __restrict__ tarw, int W, int H, int d_first, int d_end,
            const float* __restrict__ zX, const float* __restrict__ isdX,
            const float* __restrict__ zY, const float* __restrict__ isdY,
            float* __restrict__ C, int out_w, int64_t out_pitch,
@@ -133,7 +133,7 @@ ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
   float* Bs = sm + G::ROWS * G::AW;       // [ROWS][BW]
   const int x0 = blockIdx.x * NC_TX;
   const int y0 = blockIdx.y * NC_TY;
-  const int d0 = blockIdx.z * NC_DC;
+  const int d0 = d_first + blockIdx.z * NC_DC;
   const int SW = W + 2 * r;
   // image column of A[.][0] and B[.][0]
   //   anchor 0: A = X' at x + j - r, B = Y' at x - d + j - r
@@ -195,7 +195,7 @@ ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
 #pragma unroll
           for (int k = 0; k < NC_DW; ++k) {
             const int d = d0 + wave * NC_DW + k;
-            if (d >= D) continue;
+            if (d >= d_end) continue;
             // rows y-r .. y+r sit in ring slots (s+1) .. (s+K) mod K, in order
             float S = ring[k][(s + 1) % K];
 #pragma unroll
@@ -204,7 +204,7 @@ ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
             const float zB = anchor ? zX[rowo + cb] : zY[rowo + cb];
             const float iB = anchor ? isdX[rowo + cb] : isdY[rowo + cb];
             const float c = fmaf(-S * iA, iB, fmaf(zA, zB, 1.0f));
-            C[(int64_t)d * out_slice + (int64_t)y * out_pitch + x] = c;
+            C[(int64_t)(d - d_first) * out_slice + (int64_t)y * out_pitch + x] = c;
           }
         }
       }
@@ -216,12 +216,12 @@ template <int r, typename T>
 hipError_t launch_ncc_r(const Plan& P, const T* ref, const float* tar_w, const float* zX,
                         const float* isdX, const float* zY, const float* isdY, float* C,
                         int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
-                        hipStream_t s) {
+                        int d_first, int d_end, hipStream_t s) {
   dim3 grid((out_w + NC_TX - 1) / NC_TX, (P.H + NC_TY - 1) / NC_TY,
-            (P.D + NC_DC - 1) / NC_DC);
+            (d_end - d_first + NC_DC - 1) / NC_DC);
   hipLaunchKernelGGL((ncc_kernel<r, T>), grid, dim3(256), NccGeom<r>::lds_bytes, s, ref,
-                     P.p.pitch_ref, tar_w, P.W, P.H, P.D, zX, isdX, zY, isdY, C, out_w,
-                     out_pitch, out_slice, anchor);
+                     P.p.pitch_ref, tar_w, P.W, P.H, d_first, d_end, zX, isdX, zY, isdY, C,
+                     out_w, out_pitch, out_slice, anchor);
   return hipGetLastError();
 }
 
@@ -229,10 +229,10 @@ template <typename T>
 hipError_t launch_ncc_t(const Plan& P, const T* ref, const float* tar_w, const float* zX,
                         const float* isdX, const float* zY, const float* isdY, float* C,
                         int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
-                        hipStream_t s) {
+                        int d_first, int d_end, hipStream_t s) {
 #define NCC_CASE(R_) \
   case R_: return launch_ncc_r<R_, T>(P, ref, tar_w, zX, isdX, zY, isdY, C, out_w, \
-                                      out_pitch, out_slice, anchor, s);
+                                      out_pitch, out_slice, anchor, d_first, d_end, s);
   switch (P.r) {
     NCC_CASE(1) NCC_CASE(2) NCC_CASE(3) NCC_CASE(4)
     NCC_CASE(5) NCC_CASE(6) NCC_CASE(7) NCC_CASE(8)
@@ -275,12 +275,13 @@ hipError_t launch_block_stats(const Plan& P, const void* img, stereo_dtype dt,
 hipError_t launch_ncc(const Plan& P, const void* ref, const float* tar_w,
                       const float* zX, const float* isdX, const float* zY,
                       const float* isdY, float* C, int out_w, int64_t out_pitch,
-                      int64_t out_slice, int anchor, hipStream_t s) {
+                      int64_t out_slice, int anchor, hipStream_t s, int d_first, int d_end) {
+  if (d_end < 0) d_end = P.D;
   if (P.p.dtype == STEREO_U8)
     return launch_ncc_t(P, (const uint8_t*)ref, tar_w, zX, isdX, zY, isdY, C, out_w,
-                        out_pitch, out_slice, anchor, s);
+                        out_pitch, out_slice, anchor, d_first, d_end, s);
   return launch_ncc_t(P, (const float*)ref, tar_w, zX, isdX, zY, isdY, C, out_w, out_pitch,
-                      out_slice, anchor, s);
+                      out_slice, anchor, d_first, d_end, s);
 }
 
 }  // namespace stereo

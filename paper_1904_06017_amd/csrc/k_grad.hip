@@ -1,0 +1,846 @@
+// Adjoint kernels of the differentiable form: soft-argmin head, bilateral
+// aggregation (Eqs. 10-11), NCC cost (Eq. 8), perspective warp (Eq. 4), and
+// the photometric L1 loss.
+//
+// Determinism: every gradient is either a gather in a fixed order or a sum of
+// fixed-point integers (for the two true scatters, the warp and the loss
+// sampling of the target image), so results do not depend on scheduling.
+//
+// Domains (x = column, y = row, all row-major):
+//   image            [H][W]
+//   virtual X domain [H + 2r][W + 2r], position (y + r, x + r) for y, x in
+//                    [-r, H + r) x [-r, W + r): every place a reference block
+//                    element can be read from before clamping
+//   virtual Y domain [H + 2r][W + D - 1 + 2r], columns [-(D-1) - r, W + r):
+//                    every place a warped-target block element can be read
+//                    from (blocks centred down to column -(D-1))
+// Block reads clamp, so a gradient that lands on a virtual position belongs
+// to the clamped image pixel; the fold kernel adds it there.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace stereo {
+namespace grad {
+
+constexpr double kFix = 17592186044416.0;   // 2^44: fixed-point scale
+constexpr int kT = 256;
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+template <typename T>
+__device__ __forceinline__ float ldf(const T* p) { return static_cast<float>(*p); }
+
+__device__ __forceinline__ void fix_add(unsigned long long* dst, double v) {
+  atomicAdd(dst, (unsigned long long)(long long)llrint(v * kFix));
+}
+
+// ---------------------------------------------------------------------------
+// sum_q w(p, q) over the window truncated to the image (Eq. 11 denominator)
+template <typename GT>
+__global__ void __launch_bounds__(kT)
+weight_sum_kernel(const GT* __restrict__ g, int64_t gp, int W, int H, int R, float ks2,
+                  float kr2, float* __restrict__ Wp) {
+  const int x = blockIdx.x * kT + threadIdx.x, y = blockIdx.y;
+  if (x >= W) return;
+  const float gpx = ldf(g + (int64_t)y * gp + x);
+  float s = 0.0f;
+  for (int dy = -R; dy <= R; ++dy) {
+    const int qy = y + dy;
+    if (qy < 0 || qy >= H) continue;
+    for (int dx = -R; dx <= R; ++dx) {
+      const int qx = x + dx;
+      if (qx < 0 || qx >= W) continue;
+      const float dg = gpx - ldf(g + (int64_t)qy * gp + qx);
+      s += __builtin_amdgcn_exp2f(-(float)(dx * dx + dy * dy) * ks2 - dg * dg * kr2);
+    }
+  }
+  Wp[(int64_t)y * W + x] = s;
+}
+
+// ---------------------------------------------------------------------------
+// soft-argmin adjoint for one level tile:
+//   P = exp(-E/T - m - logZ);  dE = g' (-1/T) P (d - dh);  g' = gD (1 - c1)
+//   writes dE and dE / W_p; accumulates a_p += sum_d dE E (tile order fixed)
+__global__ void __launch_bounds__(kT)
+soft_grad_e_kernel(const float* __restrict__ Et, const float* __restrict__ sm_m,
+                   const float* __restrict__ sm_logZ, const float* __restrict__ sm_dh,
+                   const float* __restrict__ gD, const float* __restrict__ Wp, int W,
+                   int H, int d_first, int nlev, float invT, float one_minus_c1,
+                   float* __restrict__ gE, float* __restrict__ G, float* __restrict__ aP) {
+  const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int64_t HW = (int64_t)W * H;
+  if (p >= HW) return;
+  const float l2e = 1.4426950408889634f;
+  const float base = -(sm_m[p] + sm_logZ[p]);
+  const float gp = gD[p] * one_minus_c1 * (-invT);
+  const float dh = sm_dh[p];
+  const float rw = 1.0f / Wp[p];
+  float a = aP[p];
+  for (int t = 0; t < nlev; ++t) {
+    const float e = Et[t * HW + p];
+    const float P = __builtin_amdgcn_exp2f((fmaf(-e, invT, base)) * l2e);
+    const float g = gp * P * ((float)(d_first + t) - dh);
+    gE[t * HW + p] = g;
+    G[t * HW + p] = g * rw;
+    a = fmaf(g, e, a);
+  }
+  aP[p] = a;
+}
+
+// ---------------------------------------------------------------------------
+// Guide (reference image) gradient of the aggregation weights, one level tile:
+//   A1(x) += sum_q w(x,q) (G(x) - G(q)) sum_d dE(x,d) C(q,d)
+//   A2(x) += sum_q w(x,q) (G(q) - G(x)) / W_q sum_d dE(q,d) C(x,d)
+// (q over the window of x inside the image, d over the tile).  One thread
+// per pixel, 16 x 16 pixel tiles; the halo of C, dE (4 levels per quad), G
+// and 1/W is staged in LDS per quad of levels.
+constexpr int GG_T = 16;
+
+template <int R, typename GT>
+__global__ void __launch_bounds__(kT)
+guide_grad_kernel(const float* __restrict__ Ct, const float* __restrict__ gEt,
+                  const GT* __restrict__ g, int64_t gpitch, const float* __restrict__ Wp,
+                  int W, int H, int nlev, float ks2, float kr2, float* __restrict__ A1,
+                  float* __restrict__ A2) {
+  constexpr int HX = GG_T + 2 * R;
+  __shared__ float4 Cs[HX * HX];
+  __shared__ float4 Es[HX * HX];
+  __shared__ float Gs[HX * HX];
+  __shared__ float RWs[HX * HX];
+  const int t = threadIdx.x;
+  const int tx = t % GG_T, ty = t / GG_T;
+  const int x0 = blockIdx.x * GG_T, y0 = blockIdx.y * GG_T;
+  const int x = x0 + tx, y = y0 + ty;
+  const int64_t HW = (int64_t)W * H;
+  for (int i = t; i < HX * HX; i += kT) {
+    const int yy = i / HX, xx = i - yy * HX;
+    const int gy = y0 - R + yy, gx = x0 - R + xx;
+    const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+    Gs[i] = in ? ldf(g + (int64_t)gy * gpitch + gx) : 0.0f;
+    RWs[i] = in ? 1.0f / Wp[(int64_t)gy * W + gx] : 0.0f;
+  }
+  const bool me = x < W && y < H;
+  float a1 = 0.0f, a2 = 0.0f;
+  for (int q0 = 0; q0 < nlev; q0 += 4) {
+    __syncthreads();
+    for (int i = t; i < HX * HX; i += kT) {
+      const int yy = i / HX, xx = i - yy * HX;
+      const int gy = y0 - R + yy, gx = x0 - R + xx;
+      float4 c = make_float4(0.f, 0.f, 0.f, 0.f), e = c;
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+        const int64_t o = (int64_t)gy * W + gx;
+        if (q0 + 0 < nlev) { c.x = Ct[(q0 + 0) * HW + o]; e.x = gEt[(q0 + 0) * HW + o]; }
+        if (q0 + 1 < nlev) { c.y = Ct[(q0 + 1) * HW + o]; e.y = gEt[(q0 + 1) * HW + o]; }
+        if (q0 + 2 < nlev) { c.z = Ct[(q0 + 2) * HW + o]; e.z = gEt[(q0 + 2) * HW + o]; }
+        if (q0 + 3 < nlev) { c.w = Ct[(q0 + 3) * HW + o]; e.w = gEt[(q0 + 3) * HW + o]; }
+      }
+      Cs[i] = c;
+      Es[i] = e;
+    }
+    __syncthreads();
+    if (!me) continue;
+    const int ci = (ty + R) * HX + tx + R;
+    const float4 cx = Cs[ci], ex = Es[ci];
+    const float gx = Gs[ci];
+    for (int dy = -R; dy <= R; ++dy) {
+      if (y + dy < 0 || y + dy >= H) continue;
+      for (int dx = -R; dx <= R; ++dx) {
+        if (x + dx < 0 || x + dx >= W) continue;
+        const int qi = ci + dy * HX + dx;
+        const float dg = gx - Gs[qi];
+        const float w = __builtin_amdgcn_exp2f(-(float)(dx * dx + dy * dy) * ks2 - dg * dg * kr2);
+        const float4 cq = Cs[qi], eq = Es[qi];
+        const float dot1 = ex.x * cq.x + ex.y * cq.y + ex.z * cq.z + ex.w * cq.w;
+        const float dot2 = eq.x * cx.x + eq.y * cx.y + eq.z * cx.z + eq.w * cx.w;
+        a1 = fmaf(w * dg, dot1, a1);
+        a2 = fmaf(-w * dg * RWs[qi], dot2, a2);
+      }
+    }
+  }
+  if (me) {
+    A1[(int64_t)y * W + x] += a1;
+    A2[(int64_t)y * W + x] += a2;
+  }
+}
+
+// After all tiles: B1(x) = sum_q w (G(x) - G(q)), B2(x) = sum_q w (G(q) - G(x)) a_q / W_q,
+// dG(x) = 2/sigma_r^2 [ -(A1 - a_x B1) / W_x + (A2 - B2) ];  out = gX + dG.
+template <typename GT>
+__global__ void __launch_bounds__(kT)
+guide_finish_kernel(const GT* __restrict__ g, int64_t gpitch, const float* __restrict__ Wp,
+                    const float* __restrict__ aP, const float* __restrict__ A1,
+                    const float* __restrict__ A2, const float* __restrict__ gX, int W, int H,
+                    int R, float ks2, float kr2, float two_over_sr2,
+                    float* __restrict__ out) {
+  const int x = blockIdx.x * kT + threadIdx.x, y = blockIdx.y;
+  if (x >= W) return;
+  const int64_t p = (int64_t)y * W + x;
+  const float gx = ldf(g + (int64_t)y * gpitch + x);
+  float b1 = 0.0f, b2 = 0.0f;
+  for (int dy = -R; dy <= R; ++dy) {
+    const int qy = y + dy;
+    if (qy < 0 || qy >= H) continue;
+    for (int dx = -R; dx <= R; ++dx) {
+      const int qx = x + dx;
+      if (qx < 0 || qx >= W) continue;
+      const int64_t q = (int64_t)qy * W + qx;
+      const float dg = gx - ldf(g + (int64_t)qy * gpitch + qx);
+      const float w = __builtin_amdgcn_exp2f(-(float)(dx * dx + dy * dy) * ks2 - dg * dg * kr2);
+      b1 = fmaf(w, dg, b1);
+      b2 = fmaf(-w * dg, aP[q] / Wp[q], b2);
+    }
+  }
+  const float dG = two_over_sr2 * (-(A1[p] - aP[p] * b1) / Wp[p] + (A2[p] - b2));
+  out[p] = gX[p] + dG;
+}
+
+// ---------------------------------------------------------------------------
+// NCC adjoint coefficients for one level tile.  With A = -dC/n (0 for flat
+// blocks), rho = 1 - C, offset intensities (I - 128) and their block means:
+//   alpha = A isX isY, beta = A rho isX^2, gamma = A rho isY^2,
+// the gradient of the reference block element i is
+//   alpha (Y_i - muY) - beta (X_i - muX),
+// and of the target block element  alpha (X_i - muX) - gamma (Y_i - muY).
+// Per level maps: alpha, alpha muX, gamma, gamma muY; per pixel sums over
+// levels (all tiles): beta, beta muX, alpha muY.
+__global__ void __launch_bounds__(kT)
+ncc_coef_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
+                const float* __restrict__ zX, const float* __restrict__ isdX,
+                const float* __restrict__ zY, const float* __restrict__ isdY, int W, int H,
+                int r, int d_first, int nlev, float inv_n, float* __restrict__ Fa,
+                float* __restrict__ FamX, float* __restrict__ Fg, float* __restrict__ FgmY,
+                float* __restrict__ Sb, float* __restrict__ SbmX, float* __restrict__ SamY) {
+  const int x = blockIdx.x * kT + threadIdx.x, y = blockIdx.y;
+  if (x >= W) return;
+  const int64_t HW = (int64_t)W * H;
+  const int64_t p = (int64_t)y * W + x;
+  const int SW = W + 2 * r;
+  const int64_t ro = (int64_t)y * SW;
+  const float iX = isdX[ro + x + r];
+  const float mX = iX != 0.0f ? zX[ro + x + r] / iX : 0.0f;
+  float sb = Sb[p], sbm = SbmX[p], sam = SamY[p];
+  for (int t = 0; t < nlev; ++t) {
+    const int d = d_first + t;
+    const int cy = max(x - d, -r) + r;
+    const float iY = isdY[ro + cy];
+    const float mY = iY != 0.0f ? zY[ro + cy] / iY : 0.0f;
+    const bool flat = (iX == 0.0f) || (iY == 0.0f);
+    const float A = flat ? 0.0f : -gCt[t * HW + p] * inv_n;
+    const float rho = 1.0f - Ct[t * HW + p];
+    const float al = A * iX * iY;
+    const float be = A * rho * iX * iX;
+    const float ga = A * rho * iY * iY;
+    Fa[t * HW + p] = al;
+    FamX[t * HW + p] = al * mX;
+    Fg[t * HW + p] = ga;
+    FgmY[t * HW + p] = ga * mY;
+    sb += be;
+    sbm = fmaf(be, mX, sbm);
+    sam = fmaf(al, mY, sam);
+  }
+  Sb[p] = sb;
+  SbmX[p] = sbm;
+  SamY[p] = sam;
+}
+
+// Box sums onto the virtual X domain: B(j) = sum_{o in [-r,r]^2} F(j - o) over
+// image pixels j - o.  One lane per virtual column, walking down the rows with
+// a ring of 2r+1 horizontal sums (fixed order: horizontal j = -r..r, then
+// vertical i = -r..r).  grid.z indexes the maps (level-major).
+constexpr int BX_TX = 64, BX_TY = 32;
+
+template <int r>
+__global__ void __launch_bounds__(64)
+box_kernel(const float* __restrict__ F, int W, int H, float* __restrict__ B) {
+  constexpr int K = 2 * r + 1;
+  const int WV = W + 2 * r, HV = H + 2 * r;
+  const int64_t HW = (int64_t)W * H;
+  const float* f = F + blockIdx.z * HW;
+  float* b = B + (int64_t)blockIdx.z * HV * WV;
+  const int jx = (int)(blockIdx.x * BX_TX + threadIdx.x) - r;     // virtual column
+  const int jy0 = (int)(blockIdx.y * BX_TY) - r;                  // first virtual row
+  float ring[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) ring[i] = 0.0f;
+  const int rows = BX_TY + 2 * r;
+  for (int yb = 0; yb < rows; yb += K) {
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      const int yy = yb + s;
+      if (yy >= rows) break;
+      const int iy = jy0 - r + yy;                  // input row (image coords)
+      float h = 0.0f;
+      if (iy >= 0 && iy < H) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const int ix = jx + r - j;                // j - o with o_x = j - r ... (-r..r)
+          h += (ix >= 0 && ix < W) ? f[(int64_t)iy * W + ix] : 0.0f;
+        }
+      }
+      ring[s] = h;
+      const int oy = jy0 + yy - 2 * r;              // virtual row completed
+      if (yy >= 2 * r && oy < H + r && jx < W + r) {
+        float S = ring[(s + 1) % K];
+#pragma unroll
+        for (int i = 2; i <= K; ++i) S += ring[(s + i) % K];
+        b[(int64_t)(oy + r) * WV + (jx + r)] = S;
+      }
+    }
+  }
+}
+
+// gXv(j) += sum_{d in tile} Yv(j - d) B_alpha,d(j)     (virtual X domain)
+__global__ void __launch_bounds__(kT)
+assemble_x_kernel(const float* __restrict__ Ba, const float* __restrict__ tarw, int W, int H,
+                  int r, int d_first, int nlev, float* __restrict__ gXv) {
+  const int WV = W + 2 * r, HV = H + 2 * r;
+  const int vx = blockIdx.x * kT + threadIdx.x, vy = blockIdx.y;
+  if (vx >= WV) return;
+  const int y = clampi(vy - r, 0, H - 1);
+  const int64_t jv = (int64_t)vy * WV + vx;
+  const int64_t HVWV = (int64_t)HV * WV;
+  float acc = 0.0f;
+  for (int t = 0; t < nlev; ++t) {
+    const int xs = clampi(vx - r - (d_first + t), 0, W - 1);
+    acc = fmaf(tarw[(int64_t)y * W + xs] - kOffset, Ba[t * HVWV + jv], acc);
+  }
+  gXv[jv] += acc;
+}
+
+// gYv(k) += sum_{d in tile} [Xv(k+d) B_a(k+d) - B_amX(k+d) - Yv(k) B_g(k+d) + B_gmY(k+d)]
+// on the virtual Y domain; B at virtual X column k + d (zero outside it).
+template <typename T>
+__global__ void __launch_bounds__(kT)
+assemble_y_kernel(const float* __restrict__ Ba, const float* __restrict__ BamX,
+                  const float* __restrict__ Bg, const float* __restrict__ BgmY,
+                  const T* __restrict__ ref, int64_t rpitch, const float* __restrict__ tarw,
+                  int W, int H, int D, int r, int d_first, int nlev, float* __restrict__ gYv) {
+  const int WVX = W + 2 * r, HV = H + 2 * r, WVY = W + D - 1 + 2 * r;
+  const int ky = blockIdx.x * kT + threadIdx.x, vy = blockIdx.y;   // ky: Y-domain column index
+  if (ky >= WVY) return;
+  const int kx = ky - (D - 1) - r;                                  // image column of k
+  const int y = clampi(vy - r, 0, H - 1);
+  const float yv = tarw[(int64_t)y * W + clampi(kx, 0, W - 1)] - kOffset;
+  const int64_t HVWV = (int64_t)HV * WVX;
+  float acc = 0.0f;
+  for (int t = 0; t < nlev; ++t) {
+    const int jx = kx + d_first + t;                                // virtual X column
+    if (jx < -r || jx >= W + r) continue;
+    const int64_t j = (int64_t)t * HVWV + (int64_t)vy * WVX + (jx + r);
+    const float xv = ldf(ref + (int64_t)y * rpitch + clampi(jx, 0, W - 1)) - kOffset;
+    acc += fmaf(xv, Ba[j], -BamX[j]) + fmaf(-yv, Bg[j], BgmY[j]);
+  }
+  gYv[(int64_t)vy * WVY + ky] += acc;
+}
+
+// X side terms summed over all levels:
+//   gXv(j) += -B(S alpha muY)(j) - Xv(j) B(S beta)(j) + B(S beta muX)(j)
+template <typename T>
+__global__ void __launch_bounds__(kT)
+x_complete_kernel(const float* __restrict__ BSamY, const float* __restrict__ BSb,
+                  const float* __restrict__ BSbmX, const T* __restrict__ ref, int64_t rpitch,
+                  int W, int H, int r, float* __restrict__ gXv) {
+  const int WV = W + 2 * r;
+  const int vx = blockIdx.x * kT + threadIdx.x, vy = blockIdx.y;
+  if (vx >= WV) return;
+  const int64_t j = (int64_t)vy * WV + vx;
+  const float xv = ldf(ref + (int64_t)clampi(vy - r, 0, H - 1) * rpitch + clampi(vx - r, 0, W - 1)) - kOffset;
+  gXv[j] += -BSamY[j] - xv * BSb[j] + BSbmX[j];
+}
+
+// Fold a virtual domain back onto the image (clamped reads): pixel (x, y)
+// receives every virtual position that clamps to it.  left = columns of
+// padding on the left of the domain (r for X, D - 1 + r for Y).
+__global__ void __launch_bounds__(kT)
+fold_kernel(const float* __restrict__ gv, int W, int H, int r, int left,
+            float* __restrict__ out) {
+  const int x = blockIdx.x * kT + threadIdx.x, y = blockIdx.y;
+  if (x >= W) return;
+  const int WV = W + left + r;
+  const int ylo = (y == 0) ? -r : y, yhi = (y == H - 1) ? H - 1 + r : y;
+  const int xlo = (x == 0) ? -left : x, xhi = (x == W - 1) ? W - 1 + r : x;
+  float s = 0.0f;
+  for (int vy = ylo; vy <= yhi; ++vy)
+    for (int vx = xlo; vx <= xhi; ++vx) s += gv[(int64_t)(vy + r) * WV + (vx + left)];
+  out[(int64_t)y * W + x] = s;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 block reduction of three sums into partials[block][3].
+__device__ void reduce3(double a, double b, double c, double* __restrict__ partials) {
+  __shared__ double red[3][kT];
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  red[2][threadIdx.x] = c;
+  __syncthreads();
+  for (int s = kT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+      red[2][threadIdx.x] += red[2][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) {
+    const int64_t b0 = (int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * 3;
+    partials[b0 + threadIdx.x] = red[threadIdx.x][0];
+  }
+}
+
+// Warp adjoint: tar_w = (1-f) tar(i0) + f tar(i1) at X = x + dp - d_road(x + dp, v).
+// dtar scatters through fixed-point atomics; dX feeds the plane gradient:
+// dc -= dX (1, x + dp, v).
+template <typename T>
+__global__ void __launch_bounds__(kT)
+warp_adjoint_kernel(const T* __restrict__ tar, int64_t pitch, const float* __restrict__ gw,
+                    int W, int H, double dp, double c0, double c1, double c2,
+                    unsigned long long* __restrict__ gtar_fix, double* __restrict__ partials) {
+  const int x = blockIdx.x * kT + threadIdx.x, v = blockIdx.y;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (x < W) {
+    const double X = (double)x + dp - (c0 + c1 * ((double)x + dp) + c2 * (double)v);
+    int i0;
+    double f;
+    bool inside = false;
+    if (X <= 0.0) { i0 = 0; f = 0.0; }
+    else if (X >= (double)(W - 1)) { i0 = W - 1; f = 0.0; }
+    else { const double fl = floor(X); i0 = (int)fl; f = X - fl; inside = true; }
+    const int i1 = min(i0 + 1, W - 1);
+    const double g = gw[(int64_t)v * W + x];
+    const int64_t row = (int64_t)v * W;
+    fix_add(gtar_fix + row + i0, (1.0 - (double)(float)f) * g);
+    fix_add(gtar_fix + row + i1, (double)(float)f * g);
+    if (inside) {
+      const double gX = g * ((double)ldf(tar + (int64_t)v * pitch + i1) -
+                             (double)ldf(tar + (int64_t)v * pitch + i0));
+      s0 = gX; s1 = gX * ((double)x + dp); s2 = gX * (double)v;
+    }
+  }
+  reduce3(s0, s1, s2, partials);
+}
+
+// Direct plane terms of the shift back D = dh (1 - c1) + c0 + c1 (u + dp) + c2 v - dp.
+__global__ void __launch_bounds__(kT)
+plane_direct_kernel(const float* __restrict__ gD, const float* __restrict__ dh, int W, int H,
+                    double dp, double* __restrict__ partials) {
+  const int x = blockIdx.x * kT + threadIdx.x, v = blockIdx.y;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (x < W) {
+    const int64_t p = (int64_t)v * W + x;
+    const double g = gD[p];
+    s0 = g; s1 = g * ((double)x - (double)dh[p] + dp); s2 = g * (double)v;
+  }
+  reduce3(s0, s1, s2, partials);
+}
+
+// out[k] = sum of (sign_a * A[b][k]) + (sign_b * B[b][k]) over blocks, fixed tree.
+__global__ void __launch_bounds__(kT)
+plane_finish_kernel(const double* __restrict__ pa, int na, double sa,
+                    const double* __restrict__ pb, int nb, double sb,
+                    double* __restrict__ out) {
+  __shared__ double red[3][kT];
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < na; b += kT)
+    for (int k = 0; k < 3; ++k) a[k] += sa * pa[(int64_t)b * 3 + k];
+  for (int b = threadIdx.x; b < nb; b += kT)
+    for (int k = 0; k < 3; ++k) a[k] += sb * pb[(int64_t)b * 3 + k];
+  for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int s = kT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(kT)
+fix_to_float_kernel(const unsigned long long* __restrict__ fx, int64_t n, const float* __restrict__ add,
+                    float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  const double v = (double)(long long)fx[i] / kFix;
+  out[i] = (float)v + (add ? add[i] : 0.0f);
+}
+
+__global__ void __launch_bounds__(kT)
+zero_kernel(float* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
+__global__ void __launch_bounds__(kT)
+zero_u64_kernel(unsigned long long* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// Photometric L1: s = lerp(tar, v, u - D) clamped; L = mean |ref - s|.
+template <typename T>
+__device__ __forceinline__ void sample(const T* tar, int64_t pitch, int W, int v, double X,
+                                       int& i0, int& i1, double& f, bool& inside) {
+  inside = false;
+  if (X <= 0.0) { i0 = 0; f = 0.0; }
+  else if (X >= (double)(W - 1)) { i0 = W - 1; f = 0.0; }
+  else { const double fl = floor(X); i0 = (int)fl; f = X - fl; inside = true; }
+  i1 = min(i0 + 1, W - 1);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kT)
+l1_forward_kernel(const T* __restrict__ ref, const T* __restrict__ tar, int64_t pr, int64_t pt,
+                  const float* __restrict__ disp, int W, int H, double* __restrict__ partials) {
+  const int x = blockIdx.x * kT + threadIdx.x, v = blockIdx.y;
+  double s = 0.0;
+  if (x < W) {
+    int i0, i1; double f; bool in;
+    sample(tar, pt, W, v, (double)x - (double)disp[(int64_t)v * W + x], i0, i1, f, in);
+    const double sv = (1.0 - f) * ldf(tar + (int64_t)v * pt + i0) + f * ldf(tar + (int64_t)v * pt + i1);
+    s = fabs((double)ldf(ref + (int64_t)v * pr + x) - sv);
+  }
+  reduce3(s, 0.0, 0.0, partials);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kT)
+l1_backward_kernel(const T* __restrict__ ref, const T* __restrict__ tar, int64_t pr, int64_t pt,
+                   const float* __restrict__ disp, int W, int H, double scale,
+                   float* __restrict__ g_ref, float* __restrict__ g_disp,
+                   unsigned long long* __restrict__ gtar_fix) {
+  const int x = blockIdx.x * kT + threadIdx.x, v = blockIdx.y;
+  if (x >= W) return;
+  const int64_t p = (int64_t)v * W + x;
+  int i0, i1; double f; bool in;
+  sample(tar, pt, W, v, (double)x - (double)disp[p], i0, i1, f, in);
+  const double t0 = ldf(tar + (int64_t)v * pt + i0), t1 = ldf(tar + (int64_t)v * pt + i1);
+  const double sv = (1.0 - f) * t0 + f * t1;
+  const double a = (double)ldf(ref + (int64_t)v * pr + x);
+  const double sg = (a > sv ? 1.0 : (a < sv ? -1.0 : 0.0)) * scale;
+  if (g_ref) g_ref[p] = (float)sg;
+  if (g_disp) g_disp[p] = (float)(in ? sg * (t1 - t0) : 0.0);
+  if (gtar_fix) {
+    fix_add(gtar_fix + (int64_t)v * W + i0, -(1.0 - f) * sg);
+    fix_add(gtar_fix + (int64_t)v * W + i1, -f * sg);
+  }
+}
+
+}  // namespace grad
+}  // namespace stereo
+
+// ===========================================================================
+// Entry points: soft-argmin forward, its backward with per-level-tile
+// recompute of the cost volume, and the photometric L1 loss.
+namespace stereo {
+
+size_t grad_layout(Plan& P, size_t o) {
+  P.g_end = o;
+  if (P.p.dtype != STEREO_F32) return o;
+  const size_t HW = (size_t)P.W * P.H, DT = (size_t)P.grad_levels;
+  const size_t HV = P.H + 2 * P.r, WVX = P.W + 2 * P.r, WVY = P.W + P.D - 1 + 2 * P.r;
+  const size_t nb = (size_t)((P.W + 255) / 256) * P.H;
+  const size_t f4 = sizeof(float);
+  size_t sz[GR_COUNT];
+  for (int i = GR_WP; i <= GR_GTARW; ++i) sz[i] = f4 * HW;
+  sz[GR_SUMS] = 3 * f4 * HW;
+  for (int i = GR_CT; i <= GR_GCT; ++i) sz[i] = f4 * DT * HW;
+  sz[GR_FA] = 4 * f4 * DT * HW;
+  sz[GR_BA] = 4 * f4 * DT * HV * WVX;
+  sz[GR_BS] = 3 * f4 * HV * WVX;
+  sz[GR_GXV] = f4 * HV * WVX;
+  sz[GR_GYV] = f4 * HV * WVY;
+  sz[GR_GTARFIX] = sizeof(unsigned long long) * HW;
+  sz[GR_PART_A] = sizeof(double) * 3 * nb;
+  sz[GR_PART_B] = sizeof(double) * 3 * nb;
+  sz[GR_SCRATCH] = sizeof(double) * 4;
+  for (int i = 0; i < GR_COUNT; ++i) {
+    P.g_off[i] = o;
+    o = align256(o + sz[i]);
+  }
+  P.g_end = o;
+  return o;
+}
+
+}  // namespace stereo
+
+using namespace stereo;
+using namespace stereo::grad;
+
+namespace {
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+#define REQ(cond, ...) \
+  do { if (!(cond)) return fail(STEREO_ERR_INVALID_ARGUMENT, __VA_ARGS__); } while (0)
+#define HIPC(expr, what) \
+  do { stereo_status s_ = hip_check((expr), (what)); if (s_ != STEREO_OK) return s_; } while (0)
+#define LAUNCH(what, ...) \
+  do { hipLaunchKernelGGL(__VA_ARGS__); HIPC(hipGetLastError(), what); } while (0)
+
+stereo_status check_grad(const Plan& P, void* ws, size_t bytes) {
+  REQ(P.p.dtype == STEREO_F32, "the differentiable form needs an F32 plan");
+  REQ(P.p.perspective == 1, "the differentiable form needs perspective = 1");
+  REQ(ws != nullptr, "workspace is NULL");
+  if (bytes < P.ws_bytes)
+    return fail(STEREO_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < required %zu", bytes,
+                P.ws_bytes);
+  REQ((reinterpret_cast<uintptr_t>(ws) & 255) == 0, "workspace must be 256-byte aligned");
+  return STEREO_OK;
+}
+
+// Plan copy whose warp / shift-back plane is the call's plane.
+Plan with_plane(const Plan& P, const double plane[3]) {
+  Plan Q = P;
+  Q.p.plane[0] = plane[0];
+  Q.p.plane[1] = plane[1];
+  Q.p.plane[2] = plane[2];
+  return Q;
+}
+
+struct Maps {
+  float *zX, *isdX, *zY, *isdY;
+};
+Maps maps_of(const Plan& P, void* ws) {
+  float* b = at<float>(ws, P.off_stats);
+  const size_t n = (size_t)P.stats_w * P.H;
+  return {b, b + n, b + 2 * n, b + 3 * n};
+}
+
+stereo_status zero_f(float* p, int64_t n, hipStream_t s) {
+  LAUNCH("zero", zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return STEREO_OK;
+}
+
+template <int R>
+stereo_status guide_grad_r(const Plan& P, const float* Ct, const float* gEt, const float* ref,
+                           const float* Wp, int nlev, float ks2, float kr2, float* A1, float* A2,
+                           hipStream_t s) {
+  dim3 grid((P.W + 15) / 16, (P.H + 15) / 16);
+  LAUNCH("guide gradient", (guide_grad_kernel<R, float>), grid, dim3(256), 0, s, Ct, gEt, ref,
+         P.p.pitch_ref, Wp, P.W, P.H, nlev, ks2, kr2, A1, A2);
+  return STEREO_OK;
+}
+
+stereo_status guide_grad(const Plan& P, const float* Ct, const float* gEt, const float* ref,
+                         const float* Wp, int nlev, float ks2, float kr2, float* A1, float* A2,
+                         hipStream_t s) {
+  switch (P.R) {
+#define GG_CASE(R_) case R_: return guide_grad_r<R_>(P, Ct, gEt, ref, Wp, nlev, ks2, kr2, A1, A2, s);
+    GG_CASE(1) GG_CASE(2) GG_CASE(3) GG_CASE(4) GG_CASE(5) GG_CASE(6) GG_CASE(7) GG_CASE(8)
+#undef GG_CASE
+    default: return fail(STEREO_ERR_UNSUPPORTED, "bil_radius");
+  }
+}
+
+template <int r>
+stereo_status box_r(const Plan& P, const float* F, int nmaps, float* B, hipStream_t s) {
+  dim3 grid((P.W + 2 * r + 63) / 64, (P.H + 2 * r + 31) / 32, nmaps);
+  LAUNCH("box sums", (box_kernel<r>), grid, dim3(64), 0, s, F, P.W, P.H, B);
+  return STEREO_OK;
+}
+
+stereo_status box(const Plan& P, const float* F, int nmaps, float* B, hipStream_t s) {
+  switch (P.r) {
+#define BOX_CASE(R_) case R_: return box_r<R_>(P, F, nmaps, B, s);
+    BOX_CASE(1) BOX_CASE(2) BOX_CASE(3) BOX_CASE(4) BOX_CASE(5) BOX_CASE(6) BOX_CASE(7) BOX_CASE(8)
+#undef BOX_CASE
+    default: return fail(STEREO_ERR_UNSUPPORTED, "ncc_radius");
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+stereo_status stereo_soft_forward(stereo_plan_t plan, const float* ref, const float* tar,
+                                  const double plane[3], float* disp_soft, float* saved,
+                                  void* ws, size_t ws_bytes, hipStream_t stream) {
+  REQ(plan && ref && tar && plane && disp_soft && saved,
+      "plan, ref, tar, plane, disp_soft and saved must be non-NULL");
+  stereo_status st = check_grad(plan->P, ws, ws_bytes);
+  if (st != STEREO_OK) return st;
+  REQ(std::isfinite(plane[0]) && std::isfinite(plane[1]) && std::isfinite(plane[2]) &&
+          std::fabs(plane[1]) < 0.5, "plane must be finite with |c1| < 0.5");
+  const Plan P = with_plane(plan->P, plane);
+  const size_t HW = (size_t)P.W * P.H;
+  float* tarw = at<float>(ws, P.off_tarw);
+  Maps m = maps_of(P, ws);
+  float* cvol = at<float>(ws, P.off_cvol);
+  HIPC(launch_warp(P, tar, tarw, stream), "warp");
+  HIPC(launch_block_stats(P, ref, STEREO_F32, P.p.pitch_ref, m.zX, m.isdX, stream), "stats");
+  HIPC(launch_block_stats(P, tarw, STEREO_F32, P.W, m.zY, m.isdY, stream), "stats");
+  HIPC(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, cvol, P.W, P.W, (int64_t)HW, 0,
+                  stream), "ncc");
+  BilArgs a{};
+  a.C = cvol;
+  a.c_slice = (int64_t)HW;
+  a.c_pitch = P.W;
+  a.guide = ref;
+  a.guide_dt = STEREO_F32;
+  a.guide_pitch = P.p.pitch_ref;
+  a.sm_m = saved;
+  a.sm_logZ = saved + HW;
+  a.sm_dh = saved + 2 * HW;
+  a.disp = disp_soft;
+  a.plane[0] = plane[0]; a.plane[1] = plane[1]; a.plane[2] = plane[2];
+  HIPC(launch_bilateral(P, a, 2, stream), "aggregation + soft-argmin");
+  return STEREO_OK;
+}
+
+stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float* tar,
+                              const double plane[3], const float* saved, const float* grad_disp,
+                              float* grad_ref, float* grad_tar, double* grad_plane, void* ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  REQ(plan && ref && tar && plane && saved && grad_disp && grad_ref && grad_tar && grad_plane,
+      "all arguments must be non-NULL");
+  stereo_status st = check_grad(plan->P, ws, ws_bytes);
+  if (st != STEREO_OK) return st;
+  REQ(std::isfinite(plane[0]) && std::isfinite(plane[1]) && std::isfinite(plane[2]) &&
+          std::fabs(plane[1]) < 0.5, "plane must be finite with |c1| < 0.5");
+  const Plan P = with_plane(plan->P, plane);
+  const int W = P.W, H = P.H, D = P.D, r = P.r, DT = P.grad_levels;
+  const int64_t HW = (int64_t)W * H;
+  const int HV = H + 2 * r, WVX = W + 2 * r, WVY = W + D - 1 + 2 * r;
+  const int64_t HVWV = (int64_t)HV * WVX;
+  const Consts c = consts_of(P);
+  const double dp = (double)P.p.delta_p;
+  auto R_ = [&](int i) { return at<float>(ws, P.g_off[i]); };
+  float* tarw = at<float>(ws, P.off_tarw);
+  Maps m = maps_of(P, ws);
+  float *Wp = R_(GR_WP), *aP = R_(GR_AP), *A1 = R_(GR_A1), *A2 = R_(GR_A2);
+  // the three level sums are one [3][H][W] region: one box launch covers them
+  float *SamY = R_(GR_SUMS), *Sb = SamY + HW, *SbmX = SamY + 2 * HW;
+  float *gX = R_(GR_GX), *gtarw = R_(GR_GTARW);
+  float *Ct = R_(GR_CT), *Et = R_(GR_ET), *gEt = R_(GR_GET), *Gt = R_(GR_GT), *gCt = R_(GR_GCT);
+  float* Fa = R_(GR_FA);
+  float *FamX = Fa + DT * HW, *Fg = Fa + 2 * DT * HW, *FgmY = Fa + 3 * DT * HW;
+  float* Ba = R_(GR_BA);
+  float *BamX = Ba + DT * HVWV, *Bg = Ba + 2 * DT * HVWV, *BgmY = Ba + 3 * DT * HVWV;
+  float* BS = R_(GR_BS);
+  float *gXv = R_(GR_GXV), *gYv = R_(GR_GYV);
+  auto* gfix = at<unsigned long long>(ws, P.g_off[GR_GTARFIX]);
+  double* partA = at<double>(ws, P.g_off[GR_PART_A]);
+  double* partB = at<double>(ws, P.g_off[GR_PART_B]);
+  const float* sm_m = saved;
+  const float* sm_logZ = saved + HW;
+  const float* sm_dh = saved + 2 * HW;
+  const dim3 rows((W + 255) / 256, H);
+  const dim3 flat((unsigned)((HW + 255) / 256));
+  const int nb = (int)rows.x * H;
+
+  // accumulators (cleared by kernels: graph-safe)
+  for (float* z : {aP, A1, A2, SamY, Sb, SbmX}) {
+    st = zero_f(z, HW, stream);
+    if (st != STEREO_OK) return st;
+  }
+  if ((st = zero_f(gXv, HVWV, stream)) != STEREO_OK) return st;
+  if ((st = zero_f(gYv, (int64_t)HV * WVY, stream)) != STEREO_OK) return st;
+  LAUNCH("zero", zero_u64_kernel, flat, dim3(256), 0, stream, gfix, HW);
+
+  // forward state that is cheap to rebuild: warp, block statistics, weight sums
+  HIPC(launch_warp(P, tar, tarw, stream), "warp");
+  HIPC(launch_block_stats(P, ref, STEREO_F32, P.p.pitch_ref, m.zX, m.isdX, stream), "stats");
+  HIPC(launch_block_stats(P, tarw, STEREO_F32, W, m.zY, m.isdY, stream), "stats");
+  LAUNCH("weight sums", weight_sum_kernel<float>, rows, dim3(256), 0, stream, ref,
+         P.p.pitch_ref, W, H, P.R, c.ks2, c.kr2, Wp);
+
+  const float invT = 1.0f / P.p.softargmin_T;
+  const int n = (2 * r + 1) * (2 * r + 1);
+  for (int d0 = 0; d0 < D; d0 += DT) {
+    const int nl = std::min(DT, D - d0);
+    // recompute this tile of the cost volume and of the aggregated volume
+    HIPC(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, Ct, W, W, HW, 0, stream, d0,
+                    d0 + nl), "ncc tile");
+    BilArgs a{};
+    a.C = Ct; a.c_slice = HW; a.c_pitch = W;
+    a.guide = ref; a.guide_dt = STEREO_F32; a.guide_pitch = P.p.pitch_ref;
+    a.levels = nl;
+    a.E = Et;
+    HIPC(launch_bilateral(P, a, 0, stream), "aggregation tile");
+    LAUNCH("soft-argmin adjoint", soft_grad_e_kernel, flat, dim3(256), 0, stream, Et, sm_m,
+           sm_logZ, sm_dh, grad_disp, Wp, W, H, d0, nl, invT, (float)(1.0 - plane[1]), gEt, Gt,
+           aP);
+    // dC(q, d) = sum_p w(q, p) dE(p, d) / W_p  (weights are symmetric)
+    a.C = Gt;
+    a.E = gCt;
+    HIPC(launch_bilateral(P, a, 4, stream), "aggregation adjoint");
+    st = guide_grad(P, Ct, gEt, ref, Wp, nl, c.ks2, c.kr2, A1, A2, stream);
+    if (st != STEREO_OK) return st;
+    LAUNCH("ncc adjoint coefficients", ncc_coef_kernel, rows, dim3(256), 0, stream, Ct, gCt,
+           m.zX, m.isdX, m.zY, m.isdY, W, H, r, d0, nl, 1.0f / (float)n, Fa, FamX, Fg, FgmY,
+           Sb, SbmX, SamY);
+    if ((st = box(P, Fa, 4 * DT, Ba, stream)) != STEREO_OK) return st;
+    LAUNCH("ncc adjoint (reference side)", assemble_x_kernel, dim3((WVX + 255) / 256, HV),
+           dim3(256), 0, stream, Ba, tarw, W, H, r, d0, nl, gXv);
+    LAUNCH("ncc adjoint (target side)", assemble_y_kernel<float>, dim3((WVY + 255) / 256, HV),
+           dim3(256), 0, stream, Ba, BamX, Bg, BgmY, ref, P.p.pitch_ref, tarw, W, H, D, r, d0,
+           nl, gYv);
+  }
+  if ((st = box(P, SamY, 3, BS, stream)) != STEREO_OK) return st;
+  LAUNCH("ncc adjoint (level sums)", x_complete_kernel<float>, dim3((WVX + 255) / 256, HV),
+         dim3(256), 0, stream, BS, BS + HVWV, BS + 2 * HVWV, ref, P.p.pitch_ref, W, H, r, gXv);
+  LAUNCH("fold", fold_kernel, rows, dim3(256), 0, stream, gXv, W, H, r, r, gX);
+  LAUNCH("fold", fold_kernel, rows, dim3(256), 0, stream, gYv, W, H, r, D - 1 + r, gtarw);
+  LAUNCH("guide gradient", guide_finish_kernel<float>, rows, dim3(256), 0, stream, ref,
+         P.p.pitch_ref, Wp, aP, A1, A2, gX, W, H, P.R, c.ks2, c.kr2,
+         (float)(2.0 / ((double)P.p.sigma_r * P.p.sigma_r)), grad_ref);
+  LAUNCH("warp adjoint", warp_adjoint_kernel<float>, rows, dim3(256), 0, stream, tar,
+         P.p.pitch_tar, gtarw, W, H, dp, plane[0], plane[1], plane[2], gfix, partB);
+  LAUNCH("fixed point", fix_to_float_kernel, flat, dim3(256), 0, stream, gfix, HW,
+         (const float*)nullptr, grad_tar);
+  LAUNCH("plane (shift back)", plane_direct_kernel, rows, dim3(256), 0, stream, grad_disp,
+         sm_dh, W, H, dp, partA);
+  LAUNCH("plane", plane_finish_kernel, dim3(1), dim3(256), 0, stream, partA, nb, 1.0, partB, nb,
+         -1.0, grad_plane);
+  return STEREO_OK;
+}
+
+stereo_status stereo_photometric_l1(stereo_plan_t plan, const float* ref, const float* tar,
+                                    const float* disp_soft, double* loss_dev, void* ws,
+                                    size_t ws_bytes, hipStream_t stream) {
+  REQ(plan && ref && tar && disp_soft && loss_dev, "all arguments must be non-NULL");
+  stereo_status st = check_grad(plan->P, ws, ws_bytes);
+  if (st != STEREO_OK) return st;
+  const Plan& P = plan->P;
+  const dim3 rows((P.W + 255) / 256, P.H);
+  const int nb = (int)rows.x * P.H;
+  double* part = at<double>(ws, P.g_off[GR_PART_A]);
+  double* scratch = at<double>(ws, P.g_off[GR_SCRATCH]);
+  LAUNCH("l1", l1_forward_kernel<float>, rows, dim3(256), 0, stream, ref, tar, P.p.pitch_ref,
+         P.p.pitch_tar, disp_soft, P.W, P.H, part);
+  LAUNCH("l1", plane_finish_kernel, dim3(1), dim3(256), 0, stream, part, nb,
+         1.0 / ((double)P.W * P.H), (const double*)nullptr, 0, 0.0, scratch);
+  HIPC(hipMemcpyAsync(loss_dev, scratch, sizeof(double), hipMemcpyDeviceToDevice, stream),
+       "copy loss");
+  return STEREO_OK;
+}
+
+stereo_status stereo_photometric_l1_bwd(stereo_plan_t plan, const float* ref, const float* tar,
+                                        const float* disp_soft, double grad_loss, float* g_ref,
+                                        float* g_tar, float* g_disp, void* ws, size_t ws_bytes,
+                                        hipStream_t stream) {
+  REQ(plan && ref && tar && disp_soft, "plan, ref, tar and disp_soft must be non-NULL");
+  REQ(g_ref || g_tar || g_disp, "no gradient requested");
+  stereo_status st = check_grad(plan->P, ws, ws_bytes);
+  if (st != STEREO_OK) return st;
+  const Plan& P = plan->P;
+  const int64_t HW = (int64_t)P.W * P.H;
+  const dim3 rows((P.W + 255) / 256, P.H);
+  const dim3 flat((unsigned)((HW + 255) / 256));
+  auto* gfix = at<unsigned long long>(ws, P.g_off[GR_GTARFIX]);
+  if (g_tar) LAUNCH("zero", zero_u64_kernel, flat, dim3(256), 0, stream, gfix, HW);
+  LAUNCH("l1 adjoint", l1_backward_kernel<float>, rows, dim3(256), 0, stream, ref, tar,
+         P.p.pitch_ref, P.p.pitch_tar, disp_soft, P.W, P.H, grad_loss / (double)HW, g_ref, g_disp,
+         g_tar ? gfix : nullptr);
+  if (g_tar)
+    LAUNCH("fixed point", fix_to_float_kernel, flat, dim3(256), 0, stream, gfix, HW,
+           (const float*)nullptr, g_tar);
+  return STEREO_OK;
+}
+
+}  // extern "C"
