@@ -164,6 +164,7 @@ def run(args):
     }
     if args.extra:
         res["range_reduction"] = range_reduction(args, sc, ms)
+        res["fwd_bwd"] = fwd_bwd(args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, sc, args.cpu_rows)
     return res
@@ -209,6 +210,50 @@ def copy_calibration(mib):
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
                       "launches": 3}), flush=True)
+
+
+def fwd_bwd(args):
+    """Differentiable form at 1280x720 FP32, 48 levels: soft-argmin forward,
+    photometric L1, its backward and the backward of the soft head."""
+    import torch
+
+    from paper_1904_06017_amd import api
+    from synth import make_workload_pair, workload
+    w = workload("c5")
+    sc = make_workload_pair(w)
+    plan = api.Plan.from_workload(w)
+    dev = torch.device("cuda:0")
+    ref = torch.from_numpy(sc.ref).to(dev)
+    tar = torch.from_numpy(sc.tar).to(dev)
+
+    def step():
+        disp, saved = api.soft_forward(plan, ref, tar, w.plane)
+        loss = api.photometric_l1(plan, ref, tar, disp)
+        g_ref, g_tar, g_disp = api.photometric_l1_bwd(plan, ref, tar, disp, 1.0)
+        return api.backward(plan, ref, tar, w.plane, saved, g_disp), loss
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    n = max(3, args.steps // 10)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    c = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(n):
+        api.soft_forward(plan, ref, tar, w.plane)
+    b.record()
+    for _ in range(n):
+        step()
+    c.record()
+    torch.cuda.synchronize()
+    f_ms = a.elapsed_time(b) / n
+    fb_ms = b.elapsed_time(c) / n
+    el = w.width * w.height * w.num_disp
+    return dict(workload=w.name, num_disp=w.num_disp, fwd_ms=round(f_ms, 4),
+                fwd_gpd_s=round(el / (f_ms / 1e3) / 1e9, 3), fwd_bwd_ms=round(fb_ms, 4),
+                fwd_bwd_gpd_s=round(el / (fb_ms / 1e3) / 1e9, 3),
+                grad_levels=plan.get_tuning("grad_levels"))
 
 
 def main():

@@ -203,6 +203,55 @@ stereo_status stereo_road_transform(stereo_plan_t plan, const float* disp,
                                     void* ws, size_t ws_bytes,
                                     hipStream_t stream);
 
+/* ---- batched form ----------------------------------------------------------
+ * Many pairs of uneven size and disparity range (each with its own plan) in
+ * one workspace and one captured graph.  Per pair, results are bitwise those
+ * of stereo_match with the same plan.  The aggregation + WTA of both volumes
+ * of all pairs runs as one persistent launch per (R, guide type) group that
+ * takes 32x32 tiles of all pairs from a work queue, largest range first. */
+typedef struct stereo_batch_s* stereo_batch_t;
+typedef struct {
+  stereo_plan_t plan;      /* the pair's plan (copied at create)                */
+  const void* ref;         /* device images as described by the plan           */
+  const void* tar;
+  int16_t* dint_R;         /* device outputs [H][W]; valid / disp nullable      */
+  uint8_t* valid;
+  float* disp;
+} stereo_batch_item;
+
+/* Host only: copies the items, groups the tiles, sizes the workspace. */
+stereo_status stereo_batch_create(const stereo_batch_item* items, int32_t n,
+                                  stereo_batch_t* out);
+stereo_status stereo_batch_workspace_bytes(stereo_batch_t b, size_t* bytes);
+/* Tuning keys: "wg_per_cu" (persistent workgroups per CU, 1..8, default 2),
+ * "agg_levels_u8", "agg_levels_f32" (8 or 16).  Drops an instantiated graph. */
+stereo_status stereo_batch_set_tuning(stereo_batch_t b, const char* key, int32_t value);
+stereo_status stereo_batch_get_tuning(stereo_batch_t b, const char* key, int32_t* value);
+/* Enqueue the whole batch on `stream` (no graph).  The first call with a given
+ * workspace uploads the per-pair descriptors and synchronises the stream. */
+stereo_status stereo_submit_batch(stereo_batch_t b, void* ws, size_t ws_bytes,
+                                  hipStream_t stream);
+/* Upload the descriptors (synchronising `stream`) and capture the batch into a
+ * graph bound to `ws`; stereo_batch_launch replays it on any stream. */
+stereo_status stereo_batch_instantiate(stereo_batch_t b, void* ws, size_t ws_bytes,
+                                       hipStream_t stream);
+stereo_status stereo_batch_launch(stereo_batch_t b, hipStream_t stream);
+stereo_status stereo_batch_destroy(stereo_batch_t b);
+
+/* ---- autotuner ---------------------------------------------------------------
+ * Times the launch-shape variants on the caller's inputs (HIP events, median
+ * of `reps` runs, synchronous), applies the fastest and stores it in the JSON
+ * file cache_path (nullable: no cache) keyed by GPU architecture and problem
+ * shape; a cached choice is applied without timing.  best_ms (nullable)
+ * receives the time of the chosen variant.  Results never depend on the
+ * variant.  stereo_plan_autotune allocates temporary outputs (hipMalloc). */
+stereo_status stereo_plan_autotune(stereo_plan_t plan, const void* ref, const void* tar,
+                                   void* ws, size_t ws_bytes, hipStream_t stream,
+                                   const char* cache_path, int32_t reps, double* best_ms);
+stereo_status stereo_batch_autotune(stereo_batch_t b, void* ws, size_t ws_bytes,
+                                    hipStream_t stream, const char* cache_path, int32_t reps,
+                                    double* best_ms);
+
 /* ---- differentiable form (F32 plans, perspective = 1) --------------------
  * Soft-argmin head over the aggregated reference volume E_R (Eqs. 8-11):
  *   P(p,d) = softmax_d(-E_R(p,d) / T),  dh(p) = sum_d d P(p,d),

@@ -43,6 +43,11 @@ class RoadFit(Structure):
     ]
 
 
+class BatchItem(Structure):
+    _fields_ = [("plan", c_void_p), ("ref", c_void_p), ("tar", c_void_p),
+                ("dint_R", c_void_p), ("valid", c_void_p), ("disp", c_void_p)]
+
+
 class StereoError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{STATUS.get(status, status)}: {message}")
@@ -86,6 +91,18 @@ SIGNATURES = {
     "stereo_photometric_l1_bwd": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double,
                                           c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                           c_void_p]),
+    "stereo_batch_create": (c_int, [POINTER(BatchItem), c_int32, POINTER(c_void_p)]),
+    "stereo_batch_workspace_bytes": (c_int, [c_void_p, POINTER(c_size_t)]),
+    "stereo_batch_set_tuning": (c_int, [c_void_p, c_char_p, c_int32]),
+    "stereo_batch_get_tuning": (c_int, [c_void_p, c_char_p, POINTER(c_int32)]),
+    "stereo_submit_batch": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "stereo_batch_instantiate": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "stereo_batch_launch": (c_int, [c_void_p, c_void_p]),
+    "stereo_batch_destroy": (c_int, [c_void_p]),
+    "stereo_plan_autotune": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p,
+                                     c_char_p, c_int32, POINTER(c_double)]),
+    "stereo_batch_autotune": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_char_p, c_int32,
+                                      POINTER(c_double)]),
 }
 
 _lib = None

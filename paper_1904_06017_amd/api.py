@@ -290,3 +290,87 @@ def photometric_l1_bwd(plan: Plan, ref, tar, disp, grad_loss=1.0):
                                                 _p(g_disp), _p(ws), plan.workspace_bytes,
                                                 _stream()))
     return g_ref, g_tar, g_disp
+
+
+# ---- autotuner and batched form --------------------------------------------
+def autotune(plan: Plan, ref, tar, cache_path: Optional[str] = None, reps: int = 3) -> float:
+    """Time the plan's launch-shape variants on (ref, tar) and keep the fastest;
+    returns its time in ms.  Synchronous; results never depend on the choice."""
+    best = ctypes.c_double()
+    ws = plan.workspace(ref.device)
+    check(_lib.load().stereo_plan_autotune(plan.handle, _p(ref), _p(tar), _p(ws),
+                                           plan.workspace_bytes, _stream(),
+                                           cache_path.encode() if cache_path else None,
+                                           int(reps), ctypes.byref(best)))
+    return float(best.value)
+
+
+class Batch:
+    """Many pairs (each with its own plan) enqueued together; see stereo.h.
+
+    pairs: list of (plan, ref, tar).  Outputs per pair: dint_R, valid, disp.
+    """
+
+    def __init__(self, pairs, device="cuda"):
+        lib = _lib.load()
+        self.plans = [p for p, _, _ in pairs]
+        self.inputs = [(r, t) for _, r, t in pairs]
+        self.outputs = []
+        items = (_lib.BatchItem * len(pairs))()
+        for i, (plan, ref, tar) in enumerate(pairs):
+            _need(ref, plan.img_dtype, (plan.H, plan.W), f"ref[{i}]")
+            _need(tar, plan.img_dtype, (plan.H, plan.W), f"tar[{i}]")
+            o = dict(dint_R=torch.empty((plan.H, plan.W), dtype=torch.int16, device=device),
+                     valid=torch.empty((plan.H, plan.W), dtype=torch.uint8, device=device),
+                     disp=torch.empty((plan.H, plan.W), dtype=torch.float32, device=device))
+            self.outputs.append(o)
+            items[i].plan = plan.handle.value
+            items[i].ref = ref.data_ptr()
+            items[i].tar = tar.data_ptr()
+            items[i].dint_R = o["dint_R"].data_ptr()
+            items[i].valid = o["valid"].data_ptr()
+            items[i].disp = o["disp"].data_ptr()
+        h = ctypes.c_void_p()
+        check(lib.stereo_batch_create(items, len(pairs), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_size_t()
+        check(lib.stereo_batch_workspace_bytes(h, ctypes.byref(n)))
+        self.workspace_bytes = int(n.value)
+        self.ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+
+    def set_tuning(self, key, value):
+        check(_lib.load().stereo_batch_set_tuning(self._h, key.encode(), int(value)))
+
+    def get_tuning(self, key):
+        v = ctypes.c_int32()
+        check(_lib.load().stereo_batch_get_tuning(self._h, key.encode(), ctypes.byref(v)))
+        return int(v.value)
+
+    def submit(self):
+        check(_lib.load().stereo_submit_batch(self._h, _p(self.ws), self.workspace_bytes,
+                                              _stream()))
+        return self.outputs
+
+    def instantiate(self):
+        check(_lib.load().stereo_batch_instantiate(self._h, _p(self.ws), self.workspace_bytes,
+                                                   _stream()))
+
+    def launch(self):
+        check(_lib.load().stereo_batch_launch(self._h, _stream()))
+        return self.outputs
+
+    def autotune(self, cache_path=None, reps=3):
+        best = ctypes.c_double()
+        check(_lib.load().stereo_batch_autotune(self._h, _p(self.ws), self.workspace_bytes,
+                                                _stream(),
+                                                cache_path.encode() if cache_path else None,
+                                                int(reps), ctypes.byref(best)))
+        return float(best.value)
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and self._h.value:
+                _lib.load().stereo_batch_destroy(self._h)
+                self._h = ctypes.c_void_p()
+        except Exception:
+            pass

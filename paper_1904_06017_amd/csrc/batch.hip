@@ -1,0 +1,332 @@
+// Batched form: many stereo pairs of uneven size and disparity range in one
+// captured graph.  The per-pair cheap stages (warp, block statistics, NCC
+// volume, left-right check) are enqueued per pair; the dominant stage, the
+// aggregation + WTA of both cost volumes of every pair, runs as one
+// persistent launch per (radius, guide type) group that takes tiles of all
+// pairs of the group from a work queue, largest disparity range first.
+// Every tile runs the same code as the per-pair path, so each pair's result
+// is bitwise the plain path's.
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace stereo;
+
+namespace {
+
+struct Group {
+  int R;
+  stereo_dtype gdt;
+  int levels;
+  std::vector<int> tiles;     // (pair descriptor index, x0, y0) triples
+  size_t tiles_off;           // in the workspace
+};
+
+__global__ void zero_u32_kernel(unsigned int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+}  // namespace
+
+struct stereo_batch_s {
+  std::vector<stereo_batch_item> items;
+  std::vector<Plan> plans;             // copies of the pairs' plans
+  std::vector<size_t> pair_ws;         // offset of each pair's plan workspace
+  std::vector<Group> groups;
+  size_t desc_off = 0, desc_bytes = 0; // per-volume descriptors (2 per pair)
+  size_t counter_off = 0;
+  size_t ws_bytes = 0;
+  std::vector<char> host_desc;         // descriptors bound to the last workspace
+  void* bound_ws = nullptr;
+  int wg_per_cu = 2;
+  int levels_u8 = 8, levels_f32 = 8;
+  int cu_count = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture = nullptr;
+};
+
+namespace {
+
+#define BREQ(cond, ...) \
+  do { if (!(cond)) return fail(STEREO_ERR_INVALID_ARGUMENT, __VA_ARGS__); } while (0)
+#define BHIP(expr, what) \
+  do { stereo_status s_ = hip_check((expr), (what)); if (s_ != STEREO_OK) return s_; } while (0)
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+void build_layout(stereo_batch_s& b) {
+  const int n = (int)b.items.size();
+  size_t o = 0;
+  b.desc_off = o;
+  b.desc_bytes = bilateral_pair_bytes() * 2 * n;
+  o = align256(o + b.desc_bytes);
+  // groups: (R, guide type); tiles sorted by cost = D (largest first) so the
+  // queue drains with the long tiles taken first
+  b.groups.clear();
+  struct T { int cost, pair, vol, x0, y0; };
+  std::vector<std::vector<T>> per;
+  auto find_group = [&](int R, stereo_dtype g) {
+    for (size_t i = 0; i < b.groups.size(); ++i)
+      if (b.groups[i].R == R && b.groups[i].gdt == g) return (int)i;
+    Group G;
+    G.R = R; G.gdt = g;
+    G.levels = g == STEREO_U8 ? b.levels_u8 : b.levels_f32;
+    b.groups.push_back(G);
+    per.emplace_back();
+    return (int)b.groups.size() - 1;
+  };
+  for (int i = 0; i < n; ++i) {
+    const Plan& P = b.plans[i];
+    for (int vol = 0; vol < (P.p.lr_check ? 2 : 1); ++vol) {
+      const stereo_dtype g = vol == 0 ? P.p.dtype : STEREO_F32;
+      const int gi = find_group(P.R, g);
+      for (int y = 0; y < P.H; y += kBilTileH)
+        for (int x = 0; x < P.W; x += kBilTileW) per[gi].push_back({P.D, i, vol, x, y});
+    }
+  }
+  for (size_t gi = 0; gi < b.groups.size(); ++gi) {
+    std::stable_sort(per[gi].begin(), per[gi].end(),
+                     [](const T& a, const T& c) { return a.cost > c.cost; });
+    auto& tl = b.groups[gi].tiles;
+    tl.clear();
+    for (const T& t : per[gi]) {
+      tl.push_back(2 * t.pair + t.vol);
+      tl.push_back(t.x0);
+      tl.push_back(t.y0);
+    }
+    b.groups[gi].tiles_off = o;
+    o = align256(o + sizeof(int) * tl.size());
+  }
+  b.counter_off = o;
+  o = align256(o + sizeof(unsigned int) * std::max<size_t>(1, b.groups.size()));
+  b.pair_ws.resize(n);
+  for (int i = 0; i < n; ++i) {
+    b.pair_ws[i] = o;
+    o = align256(o + b.plans[i].ws_bytes);
+  }
+  b.ws_bytes = o;
+}
+
+// Descriptors depend on the workspace address; rebuilt and uploaded on bind.
+stereo_status bind(stereo_batch_s& b, void* ws, size_t bytes, hipStream_t s) {
+  BREQ(ws, "workspace is NULL");
+  if (bytes < b.ws_bytes)
+    return fail(STEREO_ERR_WORKSPACE_TOO_SMALL, "batch workspace %zu < %zu", bytes, b.ws_bytes);
+  BREQ((reinterpret_cast<uintptr_t>(ws) & 255) == 0, "workspace must be 256-byte aligned");
+  if (b.bound_ws == ws) return STEREO_OK;
+  const int n = (int)b.items.size();
+  const size_t pb = bilateral_pair_bytes();
+  b.host_desc.assign(b.desc_bytes, 0);
+  for (int i = 0; i < n; ++i) {
+    const Plan& P = b.plans[i];
+    void* pws = at<char>(ws, b.pair_ws[i]);
+    BilArgs a{};
+    a.C = at<float>(pws, P.off_cvol);
+    a.c_slice = (int64_t)P.H * P.cw;
+    a.c_pitch = P.cw;
+    a.shift = 0;
+    a.guide = b.items[i].ref;
+    a.guide_dt = P.p.dtype;
+    a.guide_pitch = P.p.pitch_ref;
+    a.dint = b.items[i].dint_R;
+    a.dsub = at<float>(pws, P.off_dsub);
+    bilateral_pair(P, a, b.host_desc.data() + (2 * i) * pb);
+    BilArgs t = a;
+    t.shift = 1;
+    t.guide = at<float>(pws, P.off_tarw);
+    t.guide_dt = STEREO_F32;
+    t.guide_pitch = P.W;
+    t.dint = at<int16_t>(pws, P.off_dT);
+    t.dsub = nullptr;
+    bilateral_pair(P, t, b.host_desc.data() + (2 * i + 1) * pb);
+  }
+  BHIP(hipMemcpyAsync(at<char>(ws, b.desc_off), b.host_desc.data(), b.desc_bytes,
+                      hipMemcpyHostToDevice, s), "upload descriptors");
+  for (const Group& G : b.groups)
+    BHIP(hipMemcpyAsync(at<char>(ws, G.tiles_off), G.tiles.data(), sizeof(int) * G.tiles.size(),
+                        hipMemcpyHostToDevice, s), "upload tiles");
+  BHIP(hipStreamSynchronize(s), "synchronise after upload");
+  b.bound_ws = ws;
+  return STEREO_OK;
+}
+
+stereo_status enqueue(stereo_batch_s& b, hipStream_t s) {
+  void* ws = b.bound_ws;
+  BREQ(ws, "batch not bound to a workspace");
+  const int n = (int)b.items.size();
+  for (int i = 0; i < n; ++i) {
+    const Plan& P = b.plans[i];
+    void* pws = at<char>(ws, b.pair_ws[i]);
+    float* tarw = at<float>(pws, P.off_tarw);
+    float* st = at<float>(pws, P.off_stats);
+    const size_t sn = (size_t)P.stats_w * P.H;
+    BHIP(launch_warp(P, b.items[i].tar, tarw, s), "batch warp");
+    BHIP(launch_block_stats(P, b.items[i].ref, P.p.dtype, P.p.pitch_ref, st, st + sn, s),
+         "batch stats");
+    BHIP(launch_block_stats(P, tarw, STEREO_F32, P.W, st + 2 * sn, st + 3 * sn, s),
+         "batch stats");
+    BHIP(launch_ncc(P, b.items[i].ref, tarw, st, st + sn, st + 2 * sn, st + 3 * sn,
+                    at<float>(pws, P.off_cvol), P.W + P.D - 1, P.cw, (int64_t)P.H * P.cw, 0, s),
+         "batch ncc");
+  }
+  unsigned int* ctr = at<unsigned int>(ws, b.counter_off);
+  const int ng = (int)b.groups.size();
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, ctr, ng);
+  BHIP(hipGetLastError(), "zero counters");
+  const void* desc = at<char>(ws, b.desc_off);
+  for (int g = 0; g < ng; ++g) {
+    const Group& G = b.groups[g];
+    const int nt = (int)G.tiles.size() / 3;
+    const int groups = std::max(1, std::min(nt, b.cu_count * b.wg_per_cu));
+    BHIP(launch_bilateral_persistent(G.R, G.gdt, G.levels, desc, at<int>(ws, G.tiles_off), nt,
+                                     ctr + g, groups, s), "batch aggregation");
+  }
+  for (int i = 0; i < n; ++i) {
+    const Plan& P = b.plans[i];
+    void* pws = at<char>(ws, b.pair_ws[i]);
+    if (b.items[i].valid || b.items[i].disp)
+      BHIP(launch_lr_check(P, b.items[i].dint_R, P.p.lr_check ? at<int16_t>(pws, P.off_dT) : nullptr,
+                           at<float>(pws, P.off_dsub), b.items[i].valid, b.items[i].disp, s),
+           "batch lr check");
+  }
+  return STEREO_OK;
+}
+
+void drop_graph(stereo_batch_s& b) {
+  if (b.exec) hipGraphExecDestroy(b.exec);
+  if (b.graph) hipGraphDestroy(b.graph);
+  b.exec = nullptr;
+  b.graph = nullptr;
+}
+
+}  // namespace
+
+namespace stereo {
+int batch_pair_count(stereo_batch_t b) { return b ? (int)b->items.size() : 0; }
+void batch_pair_shape(stereo_batch_t b, int i, int32_t* s) {
+  const Plan& P = b->plans[i];
+  s[0] = P.W; s[1] = P.H; s[2] = P.D; s[3] = P.r; s[4] = P.R; s[5] = (int32_t)P.p.dtype;
+}
+}  // namespace stereo
+
+extern "C" {
+
+stereo_status stereo_batch_create(const stereo_batch_item* items, int32_t n,
+                                  stereo_batch_t* out) {
+  BREQ(out, "out is NULL");
+  *out = nullptr;
+  BREQ(items && n >= 1, "need at least one item");
+  stereo_batch_s* b = new (std::nothrow) stereo_batch_s;
+  if (!b) return fail(STEREO_ERR_INVALID_ARGUMENT, "out of host memory");
+  for (int i = 0; i < n; ++i) {
+    const stereo_batch_item& it = items[i];
+    if (!it.plan || !it.ref || !it.tar || !it.dint_R) {
+      delete b;
+      return fail(STEREO_ERR_INVALID_ARGUMENT, "item %d: plan, ref, tar and dint_R must be set", i);
+    }
+    b->items.push_back(it);
+    b->plans.push_back(it.plan->P);
+  }
+  build_layout(*b);
+  *out = b;
+  return STEREO_OK;
+}
+
+stereo_status stereo_batch_workspace_bytes(stereo_batch_t b, size_t* bytes) {
+  BREQ(b && bytes, "batch and bytes must be non-NULL");
+  *bytes = b->ws_bytes;
+  return STEREO_OK;
+}
+
+stereo_status stereo_batch_set_tuning(stereo_batch_t b, const char* key, int32_t value) {
+  BREQ(b && key, "batch and key must be non-NULL");
+  const std::string k(key);
+  if (k == "wg_per_cu") {
+    BREQ(value >= 1 && value <= 8, "wg_per_cu must be 1..8");
+    b->wg_per_cu = value;
+  } else if (k == "agg_levels_u8" || k == "agg_levels_f32") {
+    BREQ(value == 8 || value == 16, "%s must be 8 or 16", key);
+    (k == "agg_levels_u8" ? b->levels_u8 : b->levels_f32) = value;
+    for (Group& G : b->groups) G.levels = G.gdt == STEREO_U8 ? b->levels_u8 : b->levels_f32;
+  } else {
+    return fail(STEREO_ERR_INVALID_ARGUMENT, "unknown batch tuning key '%s'", key);
+  }
+  drop_graph(*b);
+  return STEREO_OK;
+}
+
+stereo_status stereo_batch_get_tuning(stereo_batch_t b, const char* key, int32_t* value) {
+  BREQ(b && key && value, "batch, key and value must be non-NULL");
+  const std::string k(key);
+  if (k == "wg_per_cu") *value = b->wg_per_cu;
+  else if (k == "agg_levels_u8") *value = b->levels_u8;
+  else if (k == "agg_levels_f32") *value = b->levels_f32;
+  else return fail(STEREO_ERR_INVALID_ARGUMENT, "unknown batch tuning key '%s'", key);
+  return STEREO_OK;
+}
+
+stereo_status stereo_submit_batch(stereo_batch_t b, void* ws, size_t ws_bytes,
+                                  hipStream_t stream) {
+  BREQ(b, "batch is NULL");
+  if (b->cu_count == 0) {
+    int dev = 0;
+    BHIP(hipGetDevice(&dev), "hipGetDevice");
+    BHIP(hipDeviceGetAttribute(&b->cu_count, hipDeviceAttributeMultiprocessorCount, dev),
+         "CU count");
+  }
+  stereo_status s = bind(*b, ws, ws_bytes, stream);
+  if (s != STEREO_OK) return s;
+  return enqueue(*b, stream);
+}
+
+stereo_status stereo_batch_instantiate(stereo_batch_t b, void* ws, size_t ws_bytes,
+                                       hipStream_t stream) {
+  BREQ(b, "batch is NULL");
+  if (b->cu_count == 0) {
+    int dev = 0;
+    BHIP(hipGetDevice(&dev), "hipGetDevice");
+    BHIP(hipDeviceGetAttribute(&b->cu_count, hipDeviceAttributeMultiprocessorCount, dev),
+         "CU count");
+  }
+  stereo_status s = bind(*b, ws, ws_bytes, stream);
+  if (s != STEREO_OK) return s;
+  drop_graph(*b);
+  if (!b->capture) BHIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "stream");
+  BHIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "begin capture");
+  s = enqueue(*b, b->capture);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->capture, &g);
+  if (s != STEREO_OK) {
+    if (g) hipGraphDestroy(g);
+    return s;
+  }
+  BHIP(e, "end capture");
+  b->graph = g;
+  BHIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "instantiate graph");
+  return STEREO_OK;
+}
+
+stereo_status stereo_batch_launch(stereo_batch_t b, hipStream_t stream) {
+  BREQ(b && b->exec, "batch has no instantiated graph");
+  BHIP(hipGraphLaunch(b->exec, stream), "graph launch");
+  return STEREO_OK;
+}
+
+stereo_status stereo_batch_destroy(stereo_batch_t b) {
+  if (!b) return STEREO_OK;
+  drop_graph(*b);
+  if (b->capture) hipStreamDestroy(b->capture);
+  delete b;
+  return STEREO_OK;
+}
+
+}  // extern "C"

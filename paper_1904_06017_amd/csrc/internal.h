@@ -107,6 +107,17 @@ struct BilArgs {
 hipError_t launch_bilateral(const Plan& P, const BilArgs& a, int mode,
                             hipStream_t s);
 
+// Persistent aggregation (mode 1, fused WTA) over a queue of tiles of many
+// pairs: pairs = device array of per-pair descriptors (bilateral_pair), tiles
+// = device int triples (pair, x0, y0), counter = device uint zeroed before the
+// launch.  All pairs of one launch share R, the guide type and `levels`.
+hipError_t launch_bilateral_persistent(int R, stereo_dtype gdt, int levels, const void* pairs,
+                                       const int* tiles, int n_tiles, unsigned int* counter,
+                                       int n_groups, hipStream_t s);
+size_t bilateral_pair_bytes();
+void* bilateral_pair(const Plan& P, const BilArgs& a, void* out);
+constexpr int kBilTileW = 32, kBilTileH = 32;   // pixels per aggregation tile
+
 hipError_t launch_wta(const Plan& P, const float* E, int16_t* dint,
                       float* dsub, hipStream_t s);
 hipError_t launch_lr_check(const Plan& P, const int16_t* dR, const int16_t* dT,
@@ -121,6 +132,12 @@ hipError_t launch_road(const Plan& P, const float* disp, const uint8_t* mask,
                        int max_iter, float delta_t, stereo_road_fit* fit,
                        float* disp_t, double* partials, hipStream_t s);
 
+}  // namespace stereo
+
+namespace stereo {
+// Batch introspection for the autotuner: pair count and (W, H, D, r, R, dtype).
+int batch_pair_count(stereo_batch_t b);
+void batch_pair_shape(stereo_batch_t b, int i, int32_t* shape6);
 }  // namespace stereo
 
 // The opaque plan handle of the C ABI.

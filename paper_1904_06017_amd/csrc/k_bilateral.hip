@@ -1,428 +1,59 @@
-// Bilateral cost aggregation, Eqs. (10)-(11), with an optional fused
-// winner-take-all + sub-pixel epilogue (Sec. 3.2.2, Eq. 13).
-//
-// E(p, d) = sum_q w(p, q) C(q, d) / sum_q w(p, q),
-// w(p, q) = exp(-|p - q|^2 / sigma_s^2 - (G(p) - G(q))^2 / sigma_r^2),
-// q over the (2R+1)^2 window truncated to the image.
-//
-// Work decomposition (VALU-bound stencil, no matrix cores):
-//   * a workgroup owns a TW x TH pixel tile and walks the disparity range in
-//     chunks of DC levels; for each chunk the (TW+2R) x (TH+2R) halo of costs
-//     is staged in LDS as float4 quads of consecutive levels
-//     ([quad][row][col], odd row pitch so that eight lanes on consecutive
-//     rows hit eight different 16-byte bank groups);
-//   * a thread owns PX horizontally adjacent pixels x DC levels in registers;
-//     every cost quad read from LDS feeds up to PX pixels, every weight feeds
-//     DC fused multiply-adds;
-//   * weights are computed in registers.  For an 8-bit guide the range factor
-//     of Eq. (32) comes from a table over the 511 possible intensity
-//     differences, built in LDS by each workgroup (the paper keeps its tables
-//     in constant memory; LDS is the on-chip store with per-lane gathers on
-//     CDNA), times the spatial factor of Eq. (31):  w = T[dG] * ex(dx) * ey(dy).
-//     For a float guide, w = exp2(sx(dx) + sy(dy) - dG'^2) in one exponent,
-//     with the guide pre-scaled by sqrt(log2(e)) / sigma_r.
-//     Outside the image the guide is a sentinel that gives weight 0.
-// Taps are summed in raster order (dy outer, dx inner) for every pixel, so
-// the result does not depend on the tile shape.
-#include <type_traits>
-
-#include "internal.h"
+// Dispatch of the aggregation launches over the compiled window radii.
+#include "bilateral_impl.h"
 
 namespace stereo {
-namespace {
-
-constexpr int kThreads = 256;
-
-// Range table for 8-bit guides: index 512 + G(p) - G(q); entries 257..767
-// hold exp(-dG^2 / sigma_r^2), entries 768..1023 are zero and catch the
-// out-of-image sentinel G(q) = -256 (every index stays inside the table, also
-// for the sentinel on the pixel side of tiles that overhang the image).  The
-// table sits at LDS address 0 so that a lookup is one subtraction and one
-// ds_read; the guide tile is kept as int16 (4 G, a byte offset).
-constexpr int kTabSize = 1024;
-constexpr int kTabCentre = 512;
-constexpr int kOutsideG = -256;
-
-template <int R, int PX, int DC, int TYT>
-struct BilGeom {
-  static constexpr int TXT = kThreads / TYT;
-  static constexpr int TW = TXT * PX;
-  static constexpr int TH = TYT;
-  static constexpr int HX = TW + 2 * R;
-  static constexpr int HY = TH + 2 * R;
-  static constexpr int HXP = HX | 1;          // odd pitch in float4 units
-  static constexpr int NQ = DC / 4;
-  // LDS layout: [table (8-bit guide only)] [guide tile] [cost quads]
-  template <bool TAB>
-  static constexpr size_t tab_bytes() { return TAB ? sizeof(float) * kTabSize : 0; }
-  template <bool TAB>
-  static constexpr size_t guide_bytes() {
-    return ((TAB ? sizeof(int16_t) : sizeof(float)) * (size_t)HY * HX + 15) & ~size_t(15);
-  }
-  template <bool TAB>
-  static constexpr size_t lds_bytes() {
-    return tab_bytes<TAB>() + guide_bytes<TAB>() + sizeof(float4) * (size_t)NQ * HY * HXP;
-  }
-};
-
-// Outputs and epilogue constants of one launch.
-struct BilOut {
-  float* E;                         // modes 0, 4
-  int16_t* dint;                    // mode 1
-  float* dsub;                      // mode 1 (nullable)
-  float* sm_m;                      // mode 2: max_d(-E/T)
-  float* sm_logZ;                   // mode 2: log sum_d exp(-E/T - m)
-  float* sm_dh;                     // mode 2: soft level
-  float* disp;                      // mode 2: shifted back
-  float invT;
-  double delta_p, c0, c1, c2;
-};
-
-template <typename G>
-__device__ __forceinline__ float guide_at(const G* g, int64_t pitch, int x, int y) {
-  return static_cast<float>(g[(int64_t)y * pitch + x]);
-}
-
-template <int R, int PX, int DC, int TYT, typename GT, int MODE>
-__global__ void __launch_bounds__(kThreads)
-bilateral_kernel(const float* __restrict__ C, int64_t c_slice, int64_t c_pitch,
-                 int shift, const GT* __restrict__ guide, int64_t g_pitch,
-                 int W, int H, int D, float ks2, float kr2, BilOut o) {
-  using Gm = BilGeom<R, PX, DC, TYT>;
-  constexpr bool TAB = std::is_same<GT, uint8_t>::value;
-  extern __shared__ float4 lds4[];
-  char* lds = reinterpret_cast<char*>(lds4);
-  float* Tab = reinterpret_cast<float*>(lds);                             // [kTabSize]
-  float* Gs = reinterpret_cast<float*>(lds + Gm::template tab_bytes<TAB>());  // [HY][HX]
-  int16_t* Gsi = reinterpret_cast<int16_t*>(Gs);            // 4 G for 8-bit guides
-  float4* Cs = reinterpret_cast<float4*>(lds + Gm::template tab_bytes<TAB>() +
-                                         Gm::template guide_bytes<TAB>());  // [NQ][HY][HXP]
-
-  const int t = threadIdx.x;
-  const int ty = t % TYT;
-  const int tx = t / TYT;
-  const int x0 = blockIdx.x * Gm::TW;
-  const int y0 = blockIdx.y * Gm::TH;
-  const float kr = sqrtf(kr2);
-
-  for (int i = t; i < Gm::HY * Gm::HX; i += kThreads) {
-    const int yy = i / Gm::HX, xx = i - yy * Gm::HX;
-    const int gy = y0 - R + yy, gx = x0 - R + xx;
-    const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-    if (TAB)
-      Gsi[i] = (int16_t)(4 * (in ? (int)guide[(int64_t)gy * g_pitch + gx] : kOutsideG));
-    else  // pre-scaled by sqrt(kr2): the range exponent is then -(G'(p) - G'(q))^2
-      Gs[i] = in ? guide_at(guide, g_pitch, gx, gy) * kr : kFarGuide;
-  }
-  if (TAB) {
-    for (int i = t; i < kTabSize; i += kThreads) {
-      const float dg = (float)(i - kTabCentre);
-      Tab[i] = (i >= 768) ? 0.0f : __builtin_amdgcn_exp2f(-dg * dg * kr2);
-    }
-  }
-  __syncthreads();
-
-  float gp[PX];
-  int gp4[PX];
-#pragma unroll
-  for (int k = 0; k < PX; ++k) {
-    const int idx = (ty + R) * Gm::HX + tx * PX + k + R;
-    if (TAB) {
-      gp[k] = 0.0f;
-      gp4[k] = (int)Gsi[idx] + 4 * kTabCentre;
-    } else {
-      gp[k] = Gs[idx];
-      gp4[k] = 0;
-    }
-  }
-  float sx[2 * R + 1];
-#pragma unroll
-  for (int j = 0; j <= 2 * R; ++j) {
-    sx[j] = -(float)((j - R) * (j - R)) * ks2;
-    if (TAB) sx[j] = __builtin_amdgcn_exp2f(sx[j]);        // spatial factor e_x
-  }
-  // per-pixel table row: lookup address = tp[k] - 4 G(q), one subtraction
-  const char* tp[PX];
-#pragma unroll
-  for (int k = 0; k < PX; ++k) tp[k] = reinterpret_cast<const char*>(Tab) + gp4[k];
-
-  constexpr bool NORM = (MODE == 0 || MODE == 2);   // needs sum_q w(p, q)
-  float wsum[PX];
-  float rinv[PX];
-#pragma unroll
-  for (int k = 0; k < PX; ++k) { wsum[k] = 0.0f; rinv[k] = 1.0f; }
-  // running winner-take-all state per pixel (mode 1)
-  float bestE[PX], Em[PX], Ep[PX], prev[PX];
-  int bestD[PX];
-  // running soft-argmin state per pixel (mode 2), base-2 exponents:
-  // m2 = max_d z, Z = sum_d 2^(z - m2), S1 = sum_d d 2^(z - m2), z = -E log2(e) / T
-  float m2[PX], Zs[PX], S1[PX];
-#pragma unroll
-  for (int k = 0; k < PX; ++k) {
-    bestE[k] = 3.402823466e38f; Em[k] = 0.0f; Ep[k] = 0.0f; prev[k] = 0.0f; bestD[k] = 0;
-    m2[k] = -3.402823466e38f; Zs[k] = 0.0f; S1[k] = 0.0f;
-  }
-  const float zscale = -o.invT * 1.4426950408889634f;
-
-  // element step from level d to d + 1 (the target volume also moves one
-  // column to the right per level)
-  const uint32_t step = (uint32_t)c_slice + (uint32_t)shift;
-  for (int d0 = 0; d0 < D; d0 += DC) {
-    // ---- stage the cost halo of this chunk: quads of 4 consecutive levels.
-    // Lanes run along columns (coalesced loads), the four waves along rows;
-    // offsets are 32-bit from a uniform base (SGPR-based global loads).
-    {
-      const int col = t & 63;
-      const int gx = x0 - R + col;
-      const bool colok = col < Gm::HX && gx >= 0 && gx < W;
-      for (int yy = t >> 6; yy < Gm::HY; yy += kThreads / 64) {
-        if (col >= Gm::HX) continue;
-        const int gy = y0 - R + yy;
-        const bool ok = colok && gy >= 0 && gy < H;
-        const uint32_t rowoff = ok ? (uint32_t)gy * (uint32_t)c_pitch + (uint32_t)gx : 0u;
-#pragma unroll
-        for (int q = 0; q < Gm::NQ; ++q) {
-          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (ok) {
-            const int d = d0 + 4 * q;
-            const uint32_t o = rowoff + (uint32_t)d * step;
-            if (d + 0 < D) v.x = C[o];
-            if (d + 1 < D) v.y = C[o + step];
-            if (d + 2 < D) v.z = C[o + 2 * step];
-            if (d + 3 < D) v.w = C[o + 3 * step];
-          }
-          Cs[(q * Gm::HY + yy) * Gm::HXP + col] = v;
-        }
-      }
-    }
-    __syncthreads();
-
-    float acc[PX][DC];
-#pragma unroll
-    for (int k = 0; k < PX; ++k)
-#pragma unroll
-      for (int j = 0; j < DC; ++j) acc[k][j] = 0.0f;
-    const bool first = (d0 == 0);
-
-    for (int dy = 0; dy <= 2 * R; ++dy) {
-      const int row = ty + dy;
-      const float sy = -(float)((dy - R) * (dy - R)) * ks2;
-      float wx[2 * R + 1];                       // 8-bit guide: e_y * e_x(dx)
-      if (TAB) {
-        const float ey = __builtin_amdgcn_exp2f(sy);
-#pragma unroll
-        for (int j = 0; j <= 2 * R; ++j) wx[j] = ey * sx[j];
-      }
-      const float4* crow = Cs + row * Gm::HXP + tx * PX;
-      const float* grow = Gs + row * Gm::HX + tx * PX;
-      const int16_t* growi = Gsi + row * Gm::HX + tx * PX;
-      // weights of this tap row first: the lookups / exponentials are
-      // independent of each other and of the cost reads below
-      float wr[PX][2 * R + 1];
-#pragma unroll
-      for (int xx = 0; xx < PX + 2 * R; ++xx) {
-        const float gq = TAB ? 0.0f : grow[xx];
-        const int gq4 = TAB ? (int)growi[xx] : 0;
-#pragma unroll
-        for (int k = 0; k < PX; ++k) {
-          const int dx = xx - k;
-          if (dx < 0 || dx > 2 * R) continue;
-          if (TAB) {
-            wr[k][dx] = *reinterpret_cast<const float*>(tp[k] - gq4) * wx[dx];
-          } else {
-            const float g = gp[k] - gq;
-            wr[k][dx] = __builtin_amdgcn_exp2f(fmaf(-g, g, sy + sx[dx]));
-          }
-        }
-      }
-      if (NORM && first) {
-#pragma unroll
-        for (int k = 0; k < PX; ++k)
-#pragma unroll
-          for (int dx = 0; dx <= 2 * R; ++dx) wsum[k] += wr[k][dx];
-      }
-#pragma unroll
-      for (int xx = 0; xx < PX + 2 * R; ++xx) {
-        float cv[DC];
-#pragma unroll
-        for (int q = 0; q < Gm::NQ; ++q) {
-          const float4 v = crow[q * Gm::HY * Gm::HXP + xx];
-          cv[4 * q + 0] = v.x; cv[4 * q + 1] = v.y; cv[4 * q + 2] = v.z; cv[4 * q + 3] = v.w;
-        }
-#pragma unroll
-        for (int k = 0; k < PX; ++k) {
-          const int dx = xx - k;
-          if (dx < 0 || dx > 2 * R) continue;
-          const float w = wr[k][dx];
-#pragma unroll
-          for (int j = 0; j < DC; ++j) acc[k][j] = fmaf(w, cv[j], acc[k][j]);
-        }
-      }
-    }
-
-    if (NORM && first) {
-#pragma unroll
-      for (int k = 0; k < PX; ++k) rinv[k] = 1.0f / wsum[k];
-    }
-
-    const int py = y0 + ty;
-#pragma unroll
-    for (int k = 0; k < PX; ++k) {
-      const int px = x0 + tx * PX + k;
-      if (MODE == 0 || MODE == 4) {
-        // mode 0: normalised E (Eq. 11); mode 4: the weighted sum alone
-        if (py < H && px < W) {
-#pragma unroll
-          for (int j = 0; j < DC; ++j) {
-            const int d = d0 + j;
-            if (d < D) o.E[((int64_t)d * H + py) * W + px] = MODE == 0 ? acc[k][j] * rinv[k]
-                                                                       : acc[k][j];
-          }
-        }
-      } else if (MODE == 2) {
-#pragma unroll
-        for (int j = 0; j < DC; ++j) {
-          const int d = d0 + j;
-          if (d < D) {
-            const float z = acc[k][j] * rinv[k] * zscale;
-            if (z > m2[k]) {
-              const float sc = __builtin_amdgcn_exp2f(m2[k] - z);
-              Zs[k] = fmaf(Zs[k], sc, 1.0f);
-              S1[k] = fmaf(S1[k], sc, (float)d);
-              m2[k] = z;
-            } else {
-              const float e = __builtin_amdgcn_exp2f(z - m2[k]);
-              Zs[k] += e;
-              S1[k] = fmaf((float)d, e, S1[k]);
-            }
-          }
-        }
-      } else {
-        // WTA on the unnormalised sums: sum_q w(p,q) is a positive per-pixel
-        // constant, so the argmin and the scale-free parabola offset of
-        // Eq. (13) are those of E.
-#pragma unroll
-        for (int j = 0; j < DC; ++j) {
-          const int d = d0 + j;
-          if (d < D) {
-            const float e = acc[k][j];
-            if (d == bestD[k] + 1) Ep[k] = e;
-            if (e < bestE[k]) { Em[k] = prev[k]; bestE[k] = e; bestD[k] = d; }
-            prev[k] = e;
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
-
-  if (MODE == 2) {
-    // soft level dh = sum_d d P(d), saved state (m, log Z) in natural units,
-    // and the shift back D = dh - delta_p + d_road(u - dh + delta_p, v)
-    const int py = y0 + ty;
-    const float ln2 = 0.6931471805599453f;
-#pragma unroll
-    for (int k = 0; k < PX; ++k) {
-      const int px = x0 + tx * PX + k;
-      if (py < H && px < W) {
-        const int64_t pix = (int64_t)py * W + px;
-        const float dh = S1[k] / Zs[k];
-        o.sm_m[pix] = m2[k] * ln2;
-        o.sm_logZ[pix] = __builtin_amdgcn_logf(Zs[k]) * ln2;
-        o.sm_dh[pix] = dh;
-        const double dd = dh;
-        o.disp[pix] = (float)(dd - o.delta_p + (o.c0 + o.c1 * ((double)px - dd + o.delta_p) +
-                                                o.c2 * (double)py));
-      }
-    }
-  }
-
-  if (MODE == 1) {
-    const int py = y0 + ty;
-#pragma unroll
-    for (int k = 0; k < PX; ++k) {
-      const int px = x0 + tx * PX + k;
-      if (py < H && px < W) {
-        const int d = bestD[k];
-        o.dint[(int64_t)py * W + px] = (int16_t)d;
-        if (o.dsub) {
-          float off = 0.0f;
-          if (d > 0 && d < D - 1) {
-            const float den = 2.0f * Em[k] + 2.0f * Ep[k] - 4.0f * bestE[k];
-            if (den > 0.0f) off = (Em[k] - Ep[k]) / den;
-          }
-          o.dsub[(int64_t)py * W + px] = (float)d + off;
-        }
-      }
-    }
-  }
-}
-
-template <int R, int PX, int DC, int TYT, typename GT, int MODE>
-hipError_t launch_one(const Plan& P, const BilArgs& a, hipStream_t s) {
-  using Gm = BilGeom<R, PX, DC, TYT>;
-  auto kern = bilateral_kernel<R, PX, DC, TYT, GT, MODE>;
-  constexpr size_t lds = Gm::template lds_bytes<std::is_same<GT, uint8_t>::value>();
-  static bool attr_set = false;       // per instantiation; idempotent
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  dim3 grid((P.W + Gm::TW - 1) / Gm::TW, (P.H + Gm::TH - 1) / Gm::TH);
-  const Consts c = consts_of(P);
-  BilOut o;
-  o.E = a.E; o.dint = a.dint; o.dsub = a.dsub;
-  o.sm_m = a.sm_m; o.sm_logZ = a.sm_logZ; o.sm_dh = a.sm_dh; o.disp = a.disp;
-  o.invT = 1.0f / P.p.softargmin_T;
-  o.delta_p = P.p.perspective ? (double)P.p.delta_p : 0.0;
-  o.c0 = a.plane[0]; o.c1 = a.plane[1]; o.c2 = a.plane[2];
-  hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, a.C, a.c_slice,
-                     a.c_pitch, a.shift, (const GT*)a.guide, a.guide_pitch, P.W, P.H,
-                     a.levels > 0 ? a.levels : P.D, c.ks2, c.kr2, o);
-  return hipGetLastError();
-}
-
-template <int R, int DC, typename GT>
-hipError_t launch_rdg(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
-  constexpr int PX = 4, TYT = 32;
-  switch (mode) {
-    case 0: return launch_one<R, PX, DC, TYT, GT, 0>(P, a, s);
-    case 1: return launch_one<R, PX, DC, TYT, GT, 1>(P, a, s);
-    case 2: return launch_one<R, PX, DC, TYT, GT, 2>(P, a, s);
-    case 4: return launch_one<R, PX, DC, TYT, GT, 4>(P, a, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int R, int DC>
-hipError_t launch_rd(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
-  return a.guide_dt == STEREO_U8 ? launch_rdg<R, DC, uint8_t>(P, a, mode, s)
-                                 : launch_rdg<R, DC, float>(P, a, mode, s);
-}
-
-template <int R>
-hipError_t launch_r(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
-  const int dc = a.guide_dt == STEREO_U8 ? P.agg_levels_u8 : P.agg_levels_f32;
-  return dc == 16 ? launch_rd<R, 16>(P, a, mode, s) : launch_rd<R, 8>(P, a, mode, s);
-}
-
-}  // namespace
+hipError_t launch_bilateral_r1(const Plan&, const BilArgs&, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r1(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
+hipError_t launch_bilateral_r2(const Plan&, const BilArgs&, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r2(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
+hipError_t launch_bilateral_r3(const Plan&, const BilArgs&, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r3(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
+hipError_t launch_bilateral_r4(const Plan&, const BilArgs&, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r4(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
+hipError_t launch_bilateral_r5(const Plan&, const BilArgs&, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r5(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
+hipError_t launch_bilateral_r6(const Plan&, const BilArgs&, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r6(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
+hipError_t launch_bilateral_r7(const Plan&, const BilArgs&, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r7(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
+hipError_t launch_bilateral_r8(const Plan&, const BilArgs&, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r8(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
 
 hipError_t launch_bilateral(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
   switch (P.R) {
-    case 1: return launch_r<1>(P, a, mode, s);
-    case 2: return launch_r<2>(P, a, mode, s);
-    case 3: return launch_r<3>(P, a, mode, s);
-    case 4: return launch_r<4>(P, a, mode, s);
-    case 5: return launch_r<5>(P, a, mode, s);
-    case 6: return launch_r<6>(P, a, mode, s);
-    case 7: return launch_r<7>(P, a, mode, s);
-    case 8: return launch_r<8>(P, a, mode, s);
+    case 1: return launch_bilateral_r1(P, a, mode, s);
+    case 2: return launch_bilateral_r2(P, a, mode, s);
+    case 3: return launch_bilateral_r3(P, a, mode, s);
+    case 4: return launch_bilateral_r4(P, a, mode, s);
+    case 5: return launch_bilateral_r5(P, a, mode, s);
+    case 6: return launch_bilateral_r6(P, a, mode, s);
+    case 7: return launch_bilateral_r7(P, a, mode, s);
+    case 8: return launch_bilateral_r8(P, a, mode, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_bilateral_persistent(int R, stereo_dtype gdt, int levels, const void* pairs,
+                                       const int* tiles, int n_tiles, unsigned int* counter,
+                                       int n_groups, hipStream_t s) {
+  switch (R) {
+    case 1: return launch_bilateral_persistent_r1(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    case 2: return launch_bilateral_persistent_r2(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    case 3: return launch_bilateral_persistent_r3(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    case 4: return launch_bilateral_persistent_r4(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    case 5: return launch_bilateral_persistent_r5(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    case 6: return launch_bilateral_persistent_r6(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    case 7: return launch_bilateral_persistent_r7(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    case 8: return launch_bilateral_persistent_r8(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t bilateral_pair_bytes() { return sizeof(bil::BilPair); }
+
+void* bilateral_pair(const Plan& P, const BilArgs& a, void* out) {
+  *static_cast<bil::BilPair*>(out) = bil::make_pair(P, a);
+  return out;
 }
 
 }  // namespace stereo

@@ -1,0 +1,143 @@
+"""Batched form and autotuner on the GPU (through the C ABI).
+
+Each pair of a batch must be bitwise the plain per-pair path with the same
+plan; a captured graph must reproduce the eager batch on every replay, with
+eager work and synchronisations between the replays; the autotuner's choice
+must not change any result.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle.stereo as OS
+from synth import batch_workloads, make_workload_pair
+from tests import parity_rules as PR
+
+pytestmark = pytest.mark.gpu
+api = pytest.importorskip("paper_1904_06017_amd.api")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    """12 pairs across all four size classes of the 64-pair recipe, shrunk."""
+    ws = batch_workloads(scale=0.2)
+    pick = [0, 1, 2, 16, 17, 18, 40, 41, 42, 56, 57, 63]
+    pairs = []
+    for i in pick:
+        w = ws[i]
+        sc = make_workload_pair(w)
+        pairs.append((w, sc))
+    print(f"[batch] {len(pairs)} pairs, sizes {[ (w.width, w.height, w.num_disp) for w, _ in pairs]}",
+          flush=True)
+    return pairs
+
+
+def _make(pairs):
+    items = []
+    for w, sc in pairs:
+        plan = api.Plan.from_workload(w)
+        items.append((plan, torch.from_numpy(sc.ref).cuda(), torch.from_numpy(sc.tar).cuda()))
+    return items
+
+
+def test_batch_equals_plain_path(small_batch):
+    items = _make(small_batch)
+    b = api.Batch(items)
+    outs = [{k: _host(v) for k, v in o.items()} for o in b.submit()]
+    for (plan, ref, tar), o in zip(items, outs):
+        m = api.match(plan, ref, tar)
+        assert np.array_equal(_host(m["dint_R"]), o["dint_R"])
+        assert np.array_equal(_host(m["valid"]), o["valid"])
+        assert np.array_equal(_host(m["disp"]), o["disp"], equal_nan=True)
+
+
+def test_batch_graph_replays(small_batch):
+    items = _make(small_batch)
+    b = api.Batch(items)
+    eager = [{k: _host(v) for k, v in o.items()} for o in b.submit()]
+    b.instantiate()
+    for rep in range(3):
+        for o in b.outputs:              # eager work between replays
+            o["dint_R"].fill_(-1)
+            o["disp"].zero_()
+        torch.cuda.synchronize()
+        outs = b.launch()
+        got = [{k: _host(v) for k, v in o.items()} for o in outs]
+        for e, g in zip(eager, got):
+            for k in e:
+                assert np.array_equal(e[k], g[k], equal_nan=True), (rep, k)
+
+
+def test_batch_tuning_does_not_change_results(small_batch):
+    items = _make(small_batch)
+    b = api.Batch(items)
+    ref = [{k: _host(v) for k, v in o.items()} for o in b.submit()]
+    for wg, lv in ((1, 16), (4, 8)):
+        b.set_tuning("wg_per_cu", wg)
+        b.set_tuning("agg_levels_u8", lv)
+        b.set_tuning("agg_levels_f32", lv)
+        got = [{k: _host(v) for k, v in o.items()} for o in b.submit()]
+        for e, g in zip(ref, got):
+            for k in e:
+                assert np.array_equal(e[k], g[k], equal_nan=True), (wg, lv, k)
+
+
+def test_batch_pairs_match_the_oracle(small_batch):
+    items = _make(small_batch[:3])
+    b = api.Batch(items)
+    outs = b.submit()
+    for (w, sc), o in zip(small_batch[:3], outs):
+        ora = OS.match(sc.ref, sc.tar, w, keep_volumes=True)
+        tie = PR.top2_gap(ora["E_R"]) < PR.TIE_GAP
+        dR = _host(o["dint_R"])
+        assert not np.any((dR != ora["dint_R"]) & ~tie)
+
+
+def test_plan_autotune_and_cache(small_batch, tmp_path):
+    w, sc = small_batch[-1]
+    plan = api.Plan.from_workload(w)
+    ref, tar = torch.from_numpy(sc.ref).cuda(), torch.from_numpy(sc.tar).cuda()
+    before = {k: _host(v) for k, v in api.match(plan, ref, tar).items()}
+    cache = str(tmp_path / "tune.json")
+    ms = api.autotune(plan, ref, tar, cache, reps=2)
+    assert ms > 0 and os.path.exists(cache)
+    entries = json.load(open(cache))
+    assert len(entries) == 1
+    key = next(iter(entries))
+    assert "gfx" in key and f"W={w.width}" in key
+    chosen = (plan.get_tuning("agg_levels_u8"), plan.get_tuning("agg_levels_f32"))
+    assert chosen == (int(entries[key]["agg_levels_u8"]), int(entries[key]["agg_levels_f32"]))
+    plan2 = api.Plan.from_workload(w)
+    api.autotune(plan2, ref, tar, cache, reps=2)        # cached: applied without timing
+    assert (plan2.get_tuning("agg_levels_u8"), plan2.get_tuning("agg_levels_f32")) == chosen
+    after = {k: _host(v) for k, v in api.match(plan, ref, tar).items()}
+    for k in before:
+        assert np.array_equal(before[k], after[k], equal_nan=True)
+
+
+def test_batch_autotune(small_batch, tmp_path):
+    items = _make(small_batch[:6])
+    b = api.Batch(items)
+    ref = [{k: _host(v) for k, v in o.items()} for o in b.submit()]
+    cache = str(tmp_path / "btune.json")
+    ms = b.autotune(cache, reps=1)
+    assert ms > 0
+    assert "batch" in next(iter(json.load(open(cache))))
+    got = [{k: _host(v) for k, v in o.items()} for o in b.submit()]
+    for e, g in zip(ref, got):
+        for k in e:
+            assert np.array_equal(e[k], g[k], equal_nan=True)
