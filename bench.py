@@ -36,7 +36,7 @@ def _sha(path):
 def _traffic(kernel_src, launches_bytes_key):
     """HBM bytes per launch from committed rocprofv3 counter summaries, only
     if the kernel source is unchanged since they were taken."""
-    f = os.path.join(ROOT, "profiles", "traffic_bilateral_c3a.json")
+    f = os.path.join(ROOT, "profiles", "traffic_bilateral_road1280x720_d64_persp.json")
     if not os.path.exists(f):
         return None
     d = json.load(open(f))
@@ -46,20 +46,90 @@ def _traffic(kernel_src, launches_bytes_key):
 
 
 def cpu_baseline(w, sc, rows):
-    import numpy as np
-    import oracle.stereo as OS
     from dataclasses import replace
+
+    from threadpoolctl import threadpool_limits
+
+    import oracle.stereo as OS
     ws = replace(w, height=rows)
-    t0 = time.perf_counter()
-    OS.match(sc.ref[:rows], sc.tar[:rows], ws)
-    dt = time.perf_counter() - t0
+    with threadpool_limits(limits=1):        # the oracle as written: one core
+        t0 = time.perf_counter()
+        OS.match(sc.ref[:rows], sc.tar[:rows], ws)
+        dt = time.perf_counter() - t0
     return dict(value=w.width * rows * w.num_disp / dt / 1e9, unit="G pixel·disparities/s",
                 cores=1, kind="oracle", seconds=round(dt, 2),
                 sample=f"rows 0..{rows - 1} of the {w.width}x{w.height} pair, D={w.num_disp}, "
                        f"full plain path (FP64 numpy, single thread)")
 
 
+def _gen(w):
+    from synth import make_workload_pair
+    sc = make_workload_pair(w)
+    return sc.ref, sc.tar
+
+
+def batch_scenes():
+    """The 64 seeded pairs of the mixed batch, generated on host cores (a
+    process pool started before the GPU is touched)."""
+    import multiprocessing as mp
+    from synth import batch_workloads
+    ws = batch_workloads()
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        imgs = pool.map(_gen, ws)
+    return ws, imgs
+
+
+def batched(args, scenes):
+    """64 pairs of mixed size / range / roll: one captured graph (persistent
+    aggregation over all pairs' tiles) vs the plain per-pair path."""
+    import torch
+
+    from paper_1904_06017_amd import api
+    ws, imgs = scenes
+    dev = torch.device("cuda:0")
+    items = []
+    for w, (ref, tar) in zip(ws, imgs):
+        items.append((api.Plan.from_workload(w), torch.from_numpy(ref).to(dev),
+                      torch.from_numpy(tar).to(dev)))
+    el = sum(w.width * w.height * w.num_disp for w in ws)
+    b = api.Batch(items)
+    b.submit()
+    tuned_ms = b.autotune(None, reps=2)
+    b.instantiate()
+    b.launch()
+    torch.cuda.synchronize()
+    n = max(3, args.steps // 10)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(n):
+        b.launch()
+    e[1].record()
+    outs = [dict(dint_R=torch.empty_like(o["dint_R"]), dsub=torch.empty_like(o["disp"]),
+                 valid=torch.empty_like(o["valid"]), disp=torch.empty_like(o["disp"]))
+            for o in b.outputs]
+    for (plan, ref, tar), o in zip(items, outs):     # warm the per-pair path
+        api.match(plan, ref, tar, out=o)
+    torch.cuda.synchronize()
+    e[1].record()
+    for _ in range(n):
+        for (plan, ref, tar), o in zip(items, outs):
+            api.match(plan, ref, tar, out=o)
+    e[2].record()
+    torch.cuda.synchronize()
+    t_b = e[0].elapsed_time(e[1]) / n
+    t_p = e[1].elapsed_time(e[2]) / n
+    same = all(torch.equal(o["dint_R"], p["dint_R"]) for o, p in zip(b.outputs, outs))
+    return dict(pairs=len(ws), elements=el, batch_ms=round(t_b, 3),
+                batch_gpd_s=round(el / (t_b / 1e3) / 1e9, 3), per_pair_ms=round(t_p, 3),
+                per_pair_gpd_s=round(el / (t_p / 1e3) / 1e9, 3),
+                speedup_vs_per_pair=round(t_p / t_b, 3), equal_to_per_pair=bool(same),
+                tuning={k: b.get_tuning(k) for k in ("wg_per_cu", "agg_levels_u8",
+                                                     "agg_levels_f32")},
+                autotune_best_ms=round(tuned_ms, 3))
+
+
 def run(args):
+    scenes = batch_scenes() if args.extra else None
     import torch
 
     from paper_1904_06017_amd import api
@@ -127,7 +197,7 @@ def run(args):
     flops_per_launch = 2.0 * taps * elements          # multiply-adds of Eq. (11)
     agg_s = (st["aggregate_wta_ref_ms"] + st["aggregate_wta_tar_ms"]) / 2.0 / 1e3
     achieved = flops_per_launch / agg_s / 1e12
-    src = os.path.join(ROOT, "paper_1904_06017_amd", "csrc", "k_bilateral.hip")
+    src = os.path.join(ROOT, "paper_1904_06017_amd", "csrc", "bilateral_impl.h")
     roof = dict(kernel="bilateral_kernel (aggregation + fused WTA, both volumes)",
                 bound="alu", achieved=round(achieved, 2), peak=round(MI355X_FP32_VALU_TFLOPS, 1),
                 unit="TFLOP/s", frac=round(achieved / MI355X_FP32_VALU_TFLOPS, 4),
@@ -165,6 +235,7 @@ def run(args):
     if args.extra:
         res["range_reduction"] = range_reduction(args, sc, ms)
         res["fwd_bwd"] = fwd_bwd(args)
+        res["batched"] = batched(args, scenes)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, sc, args.cpu_rows)
     return res
@@ -262,7 +333,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=96)
+    ap.add_argument("--cpu-rows", type=int, default=240)
     ap.add_argument("--no-extra", dest="extra", action="store_false")
     ap.add_argument("--tune", action="append", default=[],
                     help="plan tuning key=value (e.g. agg_levels_f32=16)")
