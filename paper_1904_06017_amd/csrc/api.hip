@@ -94,7 +94,7 @@ void layout(Plan& P) {
   size_t o = 0;
   P.off_tarw = o;  o = align256(o + sizeof(float) * (size_t)W * H);
   P.off_stats = o; o = align256(o + sizeof(float) * 4 * (size_t)P.stats_w * H);
-  P.off_cvol = o;  o = align256(o + sizeof(float) * (size_t)D * H * P.cw);
+  P.off_cvol = o;  o = align256(o + sizeof(float) * 4 * (size_t)((D + 3) / 4) * H * P.cw);
   P.off_dT = o;    o = align256(o + sizeof(int16_t) * (size_t)W * H);
   P.off_dsub = o;  o = align256(o + sizeof(float) * (size_t)W * H);
   P.off_road = o;  o = align256(o + sizeof(double) * 10 * (size_t)P.road_blocks);
@@ -317,17 +317,19 @@ stereo_status stereo_match_profiled(stereo_plan_t plan, const void* ref, const v
              "block statistics (tar_w)");
   STEREO_HIP(mark(2), "event record");
   // One reference-anchored volume over the extended columns [0, W + D - 1):
-  // the target volume is its re-indexing C_T(x, d) = C_R(x + d, d).
+  // the target volume is its re-indexing C_T(x, d) = C_R(x + d, d).  Stored
+  // as float4 quads of consecutive levels (slice and pitch in float4 units).
   const int64_t slice = (int64_t)P.H * P.cw;
   const int ext_w = P.W + P.D - 1;
   STEREO_HIP(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, cvol, ext_w, P.cw, slice,
-                        0, stream), "ncc");
+                        0, stream, 0, -1, 1), "ncc");
   STEREO_HIP(mark(3), "event record");
   BilArgs a{};
   a.C = cvol;
   a.c_slice = slice;
   a.c_pitch = P.cw;
   a.shift = 0;
+  a.quad = 1;
   a.guide = ref;
   a.guide_dt = P.p.dtype;
   a.guide_pitch = P.p.pitch_ref;

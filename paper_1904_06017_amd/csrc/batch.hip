@@ -134,6 +134,7 @@ stereo_status bind(stereo_batch_s& b, void* ws, size_t bytes, hipStream_t s) {
     a.c_slice = (int64_t)P.H * P.cw;
     a.c_pitch = P.cw;
     a.shift = 0;
+    a.quad = 1;
     a.guide = b.items[i].ref;
     a.guide_dt = P.p.dtype;
     a.guide_pitch = P.p.pitch_ref;
@@ -175,7 +176,8 @@ stereo_status enqueue(stereo_batch_s& b, hipStream_t s) {
     BHIP(launch_block_stats(P, tarw, STEREO_F32, P.W, st + 2 * sn, st + 3 * sn, s),
          "batch stats");
     BHIP(launch_ncc(P, b.items[i].ref, tarw, st, st + sn, st + 2 * sn, st + 3 * sn,
-                    at<float>(pws, P.off_cvol), P.W + P.D - 1, P.cw, (int64_t)P.H * P.cw, 0, s),
+                    at<float>(pws, P.off_cvol), P.W + P.D - 1, P.cw, (int64_t)P.H * P.cw, 0, s,
+                    0, -1, 1),
          "batch ncc");
   }
   unsigned int* ctr = at<unsigned int>(ws, b.counter_off);

@@ -6,22 +6,26 @@
 // q over the (2R+1)^2 window truncated to the image.
 //
 // Work decomposition (VALU-bound stencil, no matrix cores):
-//   * a workgroup owns a TW x TH pixel tile and walks the disparity range in
-//     chunks of DC levels; for each chunk the (TW+2R) x (TH+2R) halo of costs
-//     is staged in LDS as float4 quads of consecutive levels
-//     ([quad][row][col], odd row pitch so that eight lanes on consecutive
-//     rows hit eight different 16-byte bank groups);
-//   * a thread owns PX horizontally adjacent pixels x DC levels in registers;
-//     every cost quad read from LDS feeds up to PX pixels, every weight feeds
-//     DC fused multiply-adds;
-//   * weights are computed in registers.  For an 8-bit guide the range factor
-//     of Eq. (32) comes from a table over the 511 possible intensity
-//     differences, built in LDS by each workgroup (the paper keeps its tables
-//     in constant memory; LDS is the on-chip store with per-lane gathers on
-//     CDNA), times the spatial factor of Eq. (31):  w = T[dG] * ex(dx) * ey(dy).
-//     For a float guide, w = exp2(sx(dx) + sy(dy) - dG'^2) in one exponent,
-//     with the guide pre-scaled by sqrt(log2(e)) / sigma_r.
-//     Outside the image the guide is a sentinel that gives weight 0.
+//   * a 512-thread workgroup owns a 32 x 32 pixel tile and walks the
+//     disparity range in chunks of DC levels; for each chunk the
+//     (32+2R) x (32+2R) halo of costs is staged in LDS as float4 quads of
+//     consecutive levels ([quad][row][col], odd row pitch so that lanes on
+//     consecutive rows hit different 16-byte bank groups).  Two workgroups
+//     fit a CU at DC = 8 (16 waves), so one stages while the other computes;
+//   * a thread owns PX = 2 horizontally adjacent pixels x DC levels in
+//     registers; every cost quad read from LDS feeds up to 2 pixels, every
+//     weight feeds DC fused multiply-adds;
+//   * weights are computed in registers as one exponent,
+//     w = exp2(sx(dx) + sy(dy) - (G'(p) - G'(q))^2), with the guide pre-scaled
+//     by sqrt(log2(e)) / sigma_r (the paper keeps pre-computed weight tables,
+//     Eqs. 30-32, in constant memory; here the exponential is cheaper than a
+//     per-lane table gather).  Outside the image the guide is a sentinel
+//     whose weight is exactly 0.
+//   * the cost volume is read either in the planar layout [level][row][col]
+//     or in the level-quad-interleaved layout [level/4][row][col] float4 (one
+//     16-byte load per quad).  For the target volume, which is read sheared
+//     (level d from column x + d), a quad of the interleaved layout is loaded
+//     whole and its four components are written to their own columns.
 // Taps are summed in raster order (dy outer, dx inner) for every pixel, so
 // the result does not depend on the tile shape.
 #pragma once
@@ -32,17 +36,9 @@
 namespace stereo {
 namespace bil {
 
-constexpr int kThreads = 256;
-
-// Range table for 8-bit guides: index 512 + G(p) - G(q); entries 257..767
-// hold exp(-dG^2 / sigma_r^2), entries 768..1023 are zero and catch the
-// out-of-image sentinel G(q) = -256 (every index stays inside the table, also
-// for the sentinel on the pixel side of tiles that overhang the image).  The
-// table sits at LDS address 0 so that a lookup is one subtraction and one
-// ds_read; the guide tile is kept as int16 (4 G, a byte offset).
-constexpr int kTabSize = 1024;
-constexpr int kTabCentre = 512;
-constexpr int kOutsideG = -256;
+constexpr int kThreads = 512;
+constexpr int kPX = 2;      // pixels per thread along a row
+constexpr int kTYT = 32;    // thread rows = tile rows
 
 template <int R, int PX, int DC, int TYT>
 struct BilGeom {
@@ -53,16 +49,12 @@ struct BilGeom {
   static constexpr int HY = TH + 2 * R;
   static constexpr int HXP = HX | 1;          // odd pitch in float4 units
   static constexpr int NQ = DC / 4;
-  // LDS layout: [table (8-bit guide only)] [guide tile] [cost quads]
-  template <bool TAB>
-  static constexpr size_t tab_bytes() { return TAB ? sizeof(float) * kTabSize : 0; }
-  template <bool TAB>
+  // LDS layout: [guide tile (float)] [cost quads]
   static constexpr size_t guide_bytes() {
-    return ((TAB ? sizeof(int16_t) : sizeof(float)) * (size_t)HY * HX + 15) & ~size_t(15);
+    return (sizeof(float) * (size_t)HY * HX + 15) & ~size_t(15);
   }
-  template <bool TAB>
   static constexpr size_t lds_bytes() {
-    return tab_bytes<TAB>() + guide_bytes<TAB>() + sizeof(float4) * (size_t)NQ * HY * HXP;
+    return guide_bytes() + sizeof(float4) * (size_t)NQ * HY * HXP;
   }
 };
 
@@ -81,9 +73,10 @@ struct BilOut {
 
 // Everything one tile needs to know about its pair.
 struct BilPair {
-  const float* C;                   // cost slices
-  int64_t c_slice, c_pitch;
-  int shift;
+  const float* C;                   // cost volume
+  int64_t c_slice, c_pitch;         // planar: floats; quad: float4 units
+  int shift;                        // 1: level d is read from column x + d
+  int quad;                         // 1: level-quad-interleaved layout
   const void* guide;
   int64_t g_pitch;
   int W, H, D;
@@ -96,10 +89,6 @@ __device__ __forceinline__ float guide_at(const G* g, int64_t pitch, int x, int 
   return static_cast<float>(g[(int64_t)y * pitch + x]);
 }
 
-// One tile of one pair: the whole aggregation + epilogue for the TW x TH
-// pixels at (x0, y0).  Shared by the one-tile-per-workgroup kernel and the
-// persistent work-queue kernel of the batched form, so both give the same
-// bits.
 template <int R, int PX, int DC, int TYT, typename GT, int MODE>
 __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
                                                float4* lds4) {
@@ -111,13 +100,9 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
   const float ks2 = a.ks2, kr2 = a.kr2;
   const BilOut& o = a.o;
   using Gm = BilGeom<R, PX, DC, TYT>;
-  constexpr bool TAB = std::is_same<GT, uint8_t>::value;
   char* lds = reinterpret_cast<char*>(lds4);
-  float* Tab = reinterpret_cast<float*>(lds);                             // [kTabSize]
-  float* Gs = reinterpret_cast<float*>(lds + Gm::template tab_bytes<TAB>());  // [HY][HX]
-  int16_t* Gsi = reinterpret_cast<int16_t*>(Gs);            // 4 G for 8-bit guides
-  float4* Cs = reinterpret_cast<float4*>(lds + Gm::template tab_bytes<TAB>() +
-                                         Gm::template guide_bytes<TAB>());  // [NQ][HY][HXP]
+  float* Gs = reinterpret_cast<float*>(lds);                                 // [HY][HX]
+  float4* Cs = reinterpret_cast<float4*>(lds + Gm::guide_bytes());           // [NQ][HY][HXP]
 
   const int t = threadIdx.x;
   const int ty = t % TYT;
@@ -128,42 +113,17 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
     const int yy = i / Gm::HX, xx = i - yy * Gm::HX;
     const int gy = y0 - R + yy, gx = x0 - R + xx;
     const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-    if (TAB)
-      Gsi[i] = (int16_t)(4 * (in ? (int)guide[(int64_t)gy * g_pitch + gx] : kOutsideG));
-    else  // pre-scaled by sqrt(kr2): the range exponent is then -(G'(p) - G'(q))^2
-      Gs[i] = in ? guide_at(guide, g_pitch, gx, gy) * kr : kFarGuide;
-  }
-  if (TAB) {
-    for (int i = t; i < kTabSize; i += kThreads) {
-      const float dg = (float)(i - kTabCentre);
-      Tab[i] = (i >= 768) ? 0.0f : __builtin_amdgcn_exp2f(-dg * dg * kr2);
-    }
+    // pre-scaled by sqrt(kr2): the range exponent is then -(G'(p) - G'(q))^2
+    Gs[i] = in ? guide_at(guide, g_pitch, gx, gy) * kr : kFarGuide;
   }
   __syncthreads();
 
   float gp[PX];
-  int gp4[PX];
 #pragma unroll
-  for (int k = 0; k < PX; ++k) {
-    const int idx = (ty + R) * Gm::HX + tx * PX + k + R;
-    if (TAB) {
-      gp[k] = 0.0f;
-      gp4[k] = (int)Gsi[idx] + 4 * kTabCentre;
-    } else {
-      gp[k] = Gs[idx];
-      gp4[k] = 0;
-    }
-  }
+  for (int k = 0; k < PX; ++k) gp[k] = Gs[(ty + R) * Gm::HX + tx * PX + k + R];
   float sx[2 * R + 1];
 #pragma unroll
-  for (int j = 0; j <= 2 * R; ++j) {
-    sx[j] = -(float)((j - R) * (j - R)) * ks2;
-    if (TAB) sx[j] = __builtin_amdgcn_exp2f(sx[j]);        // spatial factor e_x
-  }
-  // per-pixel table row: lookup address = tp[k] - 4 G(q), one subtraction
-  const char* tp[PX];
-#pragma unroll
-  for (int k = 0; k < PX; ++k) tp[k] = reinterpret_cast<const char*>(Tab) + gp4[k];
+  for (int j = 0; j <= 2 * R; ++j) sx[j] = -(float)((j - R) * (j - R)) * ks2;
 
   constexpr bool NORM = (MODE == 0 || MODE == 2);   // needs sum_q w(p, q)
   float wsum[PX];
@@ -188,16 +148,13 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
   const uint32_t step = (uint32_t)a.c_slice + (uint32_t)a.shift;
   for (int d0 = 0; d0 < D; d0 += DC) {
     // ---- stage the cost halo of this chunk: quads of 4 consecutive levels.
-    // Lanes run along columns (coalesced loads), the four waves along rows;
-    // offsets are 32-bit from a uniform base (SGPR-based global loads).
-    {
-      const int col = t & 63;
-      const int gx = x0 - R + col;
-      const bool colok = col < Gm::HX && gx >= 0 && gx < W;
-      for (int yy = t >> 6; yy < Gm::HY; yy += kThreads / 64) {
-        if (col >= Gm::HX) continue;
-        const int gy = y0 - R + yy;
-        const bool ok = colok && gy >= 0 && gy < H;
+    // Lanes run along columns (coalesced loads); offsets are 32-bit from a
+    // uniform base.  Out-of-image halo entries are 0 (their weight is 0).
+    if (!a.quad) {
+      for (int i = t; i < Gm::HY * Gm::HX; i += kThreads) {
+        const int yy = i / Gm::HX, col = i - yy * Gm::HX;
+        const int gx = x0 - R + col, gy = y0 - R + yy;
+        const bool ok = gx >= 0 && gx < W && gy >= 0 && gy < H;
         const uint32_t rowoff = ok ? (uint32_t)gy * (uint32_t)c_pitch + (uint32_t)gx : 0u;
 #pragma unroll
         for (int q = 0; q < Gm::NQ; ++q) {
@@ -213,6 +170,51 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
           Cs[(q * Gm::HY + yy) * Gm::HXP + col] = v;
         }
       }
+    } else if (!a.shift) {
+      const float4* __restrict__ C4 = reinterpret_cast<const float4*>(C);
+      for (int i = t; i < Gm::HY * Gm::HX; i += kThreads) {
+        const int yy = i / Gm::HX, col = i - yy * Gm::HX;
+        const int gx = x0 - R + col, gy = y0 - R + yy;
+        const bool ok = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const uint32_t rowoff = ok ? (uint32_t)gy * (uint32_t)c_pitch + (uint32_t)gx : 0u;
+#pragma unroll
+        for (int q = 0; q < Gm::NQ; ++q) {
+          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (ok && d0 + 4 * q < D)
+            v = C4[(uint32_t)((d0 >> 2) + q) * (uint32_t)a.c_slice + rowoff];
+          Cs[(q * Gm::HY + yy) * Gm::HXP + col] = v;
+        }
+      }
+    } else {
+      // sheared quads: component j of the quad at extended column e holds
+      // level 4q' + j of target column e - 4q' - j; 3 extra columns per row
+      // cover the shear inside a quad
+      const float4* __restrict__ C4 = reinterpret_cast<const float4*>(C);
+      float* Csf = reinterpret_cast<float*>(Cs);
+      constexpr int HXE = Gm::HX + 3;
+      for (int i = t; i < Gm::HY * HXE; i += kThreads) {
+        const int yy = i / HXE, c = i - yy * HXE;
+        const int gy = y0 - R + yy;
+        const bool rowok = gy >= 0 && gy < H;
+#pragma unroll
+        for (int q = 0; q < Gm::NQ; ++q) {
+          const int dq = d0 + 4 * q;
+          const int e = x0 - R + c + dq;
+          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (rowok && dq < D && e >= 0 && e < (int)c_pitch)
+            v = C4[(uint32_t)(dq >> 2) * (uint32_t)a.c_slice +
+                   (uint32_t)gy * (uint32_t)c_pitch + (uint32_t)e];
+          const float comp[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int col = c - j;
+            if (col < 0 || col >= Gm::HX) continue;
+            const int x = x0 - R + col;
+            const bool ok = x >= 0 && x < W && dq + j < D;
+            Csf[((q * Gm::HY + yy) * Gm::HXP + col) * 4 + j] = ok ? comp[j] : 0.0f;
+          }
+        }
+      }
     }
     __syncthreads();
 
@@ -226,32 +228,20 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
     for (int dy = 0; dy <= 2 * R; ++dy) {
       const int row = ty + dy;
       const float sy = -(float)((dy - R) * (dy - R)) * ks2;
-      float wx[2 * R + 1];                       // 8-bit guide: e_y * e_x(dx)
-      if (TAB) {
-        const float ey = __builtin_amdgcn_exp2f(sy);
-#pragma unroll
-        for (int j = 0; j <= 2 * R; ++j) wx[j] = ey * sx[j];
-      }
       const float4* crow = Cs + row * Gm::HXP + tx * PX;
       const float* grow = Gs + row * Gm::HX + tx * PX;
-      const int16_t* growi = Gsi + row * Gm::HX + tx * PX;
-      // weights of this tap row first: the lookups / exponentials are
-      // independent of each other and of the cost reads below
+      // weights of this tap row first: the exponentials are independent of
+      // each other and of the cost reads below
       float wr[PX][2 * R + 1];
 #pragma unroll
       for (int xx = 0; xx < PX + 2 * R; ++xx) {
-        const float gq = TAB ? 0.0f : grow[xx];
-        const int gq4 = TAB ? (int)growi[xx] : 0;
+        const float gq = grow[xx];
 #pragma unroll
         for (int k = 0; k < PX; ++k) {
           const int dx = xx - k;
           if (dx < 0 || dx > 2 * R) continue;
-          if (TAB) {
-            wr[k][dx] = *reinterpret_cast<const float*>(tp[k] - gq4) * wx[dx];
-          } else {
-            const float g = gp[k] - gq;
-            wr[k][dx] = __builtin_amdgcn_exp2f(fmaf(-g, g, sy + sx[dx]));
-          }
+          const float g = gp[k] - gq;
+          wr[k][dx] = __builtin_amdgcn_exp2f(fmaf(-g, g, sy + sx[dx]));
         }
       }
       if (NORM && first) {
@@ -409,7 +399,7 @@ bilateral_persistent_kernel(const BilPair* __restrict__ pairs, const int* __rest
 inline BilPair make_pair(const Plan& P, const BilArgs& a) {
   const Consts c = consts_of(P);
   BilPair b;
-  b.C = a.C; b.c_slice = a.c_slice; b.c_pitch = a.c_pitch; b.shift = a.shift;
+  b.C = a.C; b.c_slice = a.c_slice; b.c_pitch = a.c_pitch; b.shift = a.shift; b.quad = a.quad;
   b.guide = a.guide; b.g_pitch = a.guide_pitch;
   b.W = P.W; b.H = P.H; b.D = a.levels > 0 ? a.levels : P.D;
   b.ks2 = c.ks2; b.kr2 = c.kr2;
@@ -426,7 +416,7 @@ template <int R, int PX, int DC, int TYT, typename GT, int MODE>
 hipError_t launch_one(const Plan& P, const BilArgs& a, hipStream_t s) {
   using Gm = BilGeom<R, PX, DC, TYT>;
   auto kern = bilateral_kernel<R, PX, DC, TYT, GT, MODE>;
-  constexpr size_t lds = Gm::template lds_bytes<std::is_same<GT, uint8_t>::value>();
+  constexpr size_t lds = Gm::lds_bytes();
   static bool attr_set = false;       // per instantiation; idempotent
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -445,7 +435,7 @@ hipError_t launch_persistent_one(const BilPair* pairs, const int* tiles, int n_t
                                  unsigned int* counter, int n_groups, hipStream_t s) {
   using Gm = BilGeom<R, PX, DC, TYT>;
   auto kern = bilateral_persistent_kernel<R, PX, DC, TYT, GT, MODE>;
-  constexpr size_t lds = Gm::template lds_bytes<std::is_same<GT, uint8_t>::value>();
+  constexpr size_t lds = Gm::lds_bytes();
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -459,7 +449,7 @@ hipError_t launch_persistent_one(const BilPair* pairs, const int* tiles, int n_t
 
 template <int R, int DC, typename GT>
 hipError_t launch_rdg(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
-  constexpr int PX = 4, TYT = 32;
+  constexpr int PX = kPX, TYT = kTYT;
   switch (mode) {
     case 0: return launch_one<R, PX, DC, TYT, GT, 0>(P, a, s);
     case 1: return launch_one<R, PX, DC, TYT, GT, 1>(P, a, s);
@@ -484,7 +474,7 @@ template <int R>
 hipError_t launch_persistent_r(stereo_dtype gdt, int levels, const BilPair* pairs,
                                const int* tiles, int n_tiles, unsigned int* counter,
                                int n_groups, hipStream_t s) {
-  constexpr int PX = 4, TYT = 32;
+  constexpr int PX = kPX, TYT = kTYT;
   if (gdt == STEREO_U8)
     return levels == 16 ? launch_persistent_one<R, PX, 16, TYT, uint8_t, 1>(pairs, tiles, n_tiles, counter, n_groups, s)
                         : launch_persistent_one<R, PX, 8, TYT, uint8_t, 1>(pairs, tiles, n_tiles, counter, n_groups, s);

@@ -29,7 +29,8 @@ struct Plan {
   stereo_params p;
   int W, H, D, r, R;
   int stats_w;        // block-statistics map width: columns [-r, W + r)
-  int cw;             // row pitch of the internal cost volume (>= W + D - 1)
+  int cw;             // row pitch of the internal cost volume (>= W + D - 1),
+                      // stored level-quad-interleaved: [ceil(D/4)][H][cw] float4
   size_t off_tarw, off_stats, off_cvol, off_dT, off_dsub, off_road;
   size_t ws_bytes;
   int road_blocks;    // partial-sum blocks of the road moments
@@ -76,17 +77,20 @@ hipError_t launch_block_stats(const Plan& P, const void* img, stereo_dtype dt,
 // tar_w block at x - d; anchor 1 the ref block at x + d with tar_w at x.
 // ref statistics in (zX, isdX), tar_w statistics in (zY, isdY).
 // Levels [d_first, d_end) (d_end < 0: all D), written to slice d - d_first.
+// quad = 1: level-quad-interleaved float4 layout [levels/4][H][out_pitch]
+// (out_slice, out_pitch in float4 units; d_first a multiple of 4).
 hipError_t launch_ncc(const Plan& P, const void* ref, const float* tar_w,
                       const float* zX, const float* isdX, const float* zY,
                       const float* isdY, float* C, int out_w, int64_t out_pitch,
                       int64_t out_slice, int anchor, hipStream_t s, int d_first = 0,
-                      int d_end = -1);
+                      int d_end = -1, int quad = 0);
 
 struct BilArgs {
-  const float* C;     // cost slices: C[d * c_slice + y * c_pitch + x + d*shift]
-  int64_t c_slice;
-  int64_t c_pitch;
+  const float* C;     // planar: C[d * c_slice + y * c_pitch + x + d*shift]
+  int64_t c_slice;    // quad: component d % 4 of float4
+  int64_t c_pitch;    //   C4[(d / 4) * c_slice + y * c_pitch + x + d*shift]
   int shift;          // 1: slice d is read from column x + d (target volume)
+  int quad;           // 1: level-quad-interleaved layout (c_* in float4 units)
   const void* guide;  // guide image
   stereo_dtype guide_dt;
   int64_t guide_pitch;

@@ -118,7 +118,11 @@ struct NccGeom {
   static constexpr size_t lds_bytes = sizeof(float) * (size_t)ROWS * (AW + BW);
 };
 
-template <int r, typename T>
+// QUAD = 1 writes the level-quad-interleaved layout [levels/4][H][pitch]
+// float4 (out_slice and out_pitch in float4 units; levels at or past d_end
+// inside the last quad are written as 0), QUAD = 0 the planar layout
+// [levels][H][pitch].
+template <int r, typename T, int QUAD>
 __global__ void __launch_bounds__(256)
 ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
            const float* __restrict__ tarw, int W, int H, int d_first, int d_end,
@@ -192,9 +196,11 @@ ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
           const int64_t rowo = (int64_t)y * SW;
           const float zA = anchor ? zY[rowo + cx] : zX[rowo + cx];
           const float iA = (anchor ? isdY[rowo + cx] : isdX[rowo + cx]) * inv_n;
+          float cq[NC_DW];
 #pragma unroll
           for (int k = 0; k < NC_DW; ++k) {
             const int d = d0 + wave * NC_DW + k;
+            cq[k] = 0.0f;
             if (d >= d_end) continue;
             // rows y-r .. y+r sit in ring slots (s+1) .. (s+K) mod K, in order
             float S = ring[k][(s + 1) % K];
@@ -203,8 +209,15 @@ ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
             const int cb = min(max(anchor ? x + d : x - d, -r), W - 1 + r) + r;
             const float zB = anchor ? zX[rowo + cb] : zY[rowo + cb];
             const float iB = anchor ? isdX[rowo + cb] : isdY[rowo + cb];
-            const float c = fmaf(-S * iA, iB, fmaf(zA, zB, 1.0f));
-            C[(int64_t)(d - d_first) * out_slice + (int64_t)y * out_pitch + x] = c;
+            cq[k] = fmaf(-S * iA, iB, fmaf(zA, zB, 1.0f));
+            if (!QUAD)
+              C[(int64_t)(d - d_first) * out_slice + (int64_t)y * out_pitch + x] = cq[k];
+          }
+          if (QUAD) {
+            const int q = (d0 + wave * NC_DW - d_first) >> 2;
+            if (d0 + wave * NC_DW < d_end)
+              reinterpret_cast<float4*>(C)[(int64_t)q * out_slice + (int64_t)y * out_pitch + x] =
+                  make_float4(cq[0], cq[1], cq[2], cq[3]);
           }
         }
       }
@@ -216,12 +229,17 @@ template <int r, typename T>
 hipError_t launch_ncc_r(const Plan& P, const T* ref, const float* tar_w, const float* zX,
                         const float* isdX, const float* zY, const float* isdY, float* C,
                         int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
-                        int d_first, int d_end, hipStream_t s) {
+                        int d_first, int d_end, int quad, hipStream_t s) {
   dim3 grid((out_w + NC_TX - 1) / NC_TX, (P.H + NC_TY - 1) / NC_TY,
             (d_end - d_first + NC_DC - 1) / NC_DC);
-  hipLaunchKernelGGL((ncc_kernel<r, T>), grid, dim3(256), NccGeom<r>::lds_bytes, s, ref,
-                     P.p.pitch_ref, tar_w, P.W, P.H, d_first, d_end, zX, isdX, zY, isdY, C,
-                     out_w, out_pitch, out_slice, anchor);
+  if (quad)
+    hipLaunchKernelGGL((ncc_kernel<r, T, 1>), grid, dim3(256), NccGeom<r>::lds_bytes, s, ref,
+                       P.p.pitch_ref, tar_w, P.W, P.H, d_first, d_end, zX, isdX, zY, isdY, C,
+                       out_w, out_pitch, out_slice, anchor);
+  else
+    hipLaunchKernelGGL((ncc_kernel<r, T, 0>), grid, dim3(256), NccGeom<r>::lds_bytes, s, ref,
+                       P.p.pitch_ref, tar_w, P.W, P.H, d_first, d_end, zX, isdX, zY, isdY, C,
+                       out_w, out_pitch, out_slice, anchor);
   return hipGetLastError();
 }
 
@@ -229,10 +247,10 @@ template <typename T>
 hipError_t launch_ncc_t(const Plan& P, const T* ref, const float* tar_w, const float* zX,
                         const float* isdX, const float* zY, const float* isdY, float* C,
                         int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
-                        int d_first, int d_end, hipStream_t s) {
+                        int d_first, int d_end, int quad, hipStream_t s) {
 #define NCC_CASE(R_) \
   case R_: return launch_ncc_r<R_, T>(P, ref, tar_w, zX, isdX, zY, isdY, C, out_w, \
-                                      out_pitch, out_slice, anchor, d_first, d_end, s);
+                                      out_pitch, out_slice, anchor, d_first, d_end, quad, s);
   switch (P.r) {
     NCC_CASE(1) NCC_CASE(2) NCC_CASE(3) NCC_CASE(4)
     NCC_CASE(5) NCC_CASE(6) NCC_CASE(7) NCC_CASE(8)
@@ -275,13 +293,15 @@ hipError_t launch_block_stats(const Plan& P, const void* img, stereo_dtype dt,
 hipError_t launch_ncc(const Plan& P, const void* ref, const float* tar_w,
                       const float* zX, const float* isdX, const float* zY,
                       const float* isdY, float* C, int out_w, int64_t out_pitch,
-                      int64_t out_slice, int anchor, hipStream_t s, int d_first, int d_end) {
+                      int64_t out_slice, int anchor, hipStream_t s, int d_first, int d_end,
+                      int quad) {
   if (d_end < 0) d_end = P.D;
+  if (quad && (d_first & 3)) return hipErrorInvalidValue;
   if (P.p.dtype == STEREO_U8)
     return launch_ncc_t(P, (const uint8_t*)ref, tar_w, zX, isdX, zY, isdY, C, out_w,
-                        out_pitch, out_slice, anchor, d_first, d_end, s);
+                        out_pitch, out_slice, anchor, d_first, d_end, quad, s);
   return launch_ncc_t(P, (const float*)ref, tar_w, zX, isdX, zY, isdY, C, out_w, out_pitch,
-                      out_slice, anchor, d_first, d_end, s);
+                      out_slice, anchor, d_first, d_end, quad, s);
 }
 
 }  // namespace stereo

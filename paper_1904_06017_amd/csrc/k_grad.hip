@@ -675,11 +675,12 @@ stereo_status stereo_soft_forward(stereo_plan_t plan, const float* ref, const fl
   HIPC(launch_block_stats(P, ref, STEREO_F32, P.p.pitch_ref, m.zX, m.isdX, stream), "stats");
   HIPC(launch_block_stats(P, tarw, STEREO_F32, P.W, m.zY, m.isdY, stream), "stats");
   HIPC(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, cvol, P.W, P.W, (int64_t)HW, 0,
-                  stream), "ncc");
+                  stream, 0, -1, 1), "ncc");
   BilArgs a{};
-  a.C = cvol;
+  a.C = cvol;                       // float4 quads of levels: [ceil(D/4)][H][W]
   a.c_slice = (int64_t)HW;
   a.c_pitch = P.W;
+  a.quad = 1;
   a.guide = ref;
   a.guide_dt = STEREO_F32;
   a.guide_pitch = P.p.pitch_ref;
