@@ -99,25 +99,26 @@ def batched(args, scenes):
     b.launch()
     torch.cuda.synchronize()
     n = max(3, args.steps // 10)
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     e[0].record()
     for _ in range(n):
         b.launch()
     e[1].record()
+    torch.cuda.synchronize()
+    t_b = e[0].elapsed_time(e[1]) / n
     outs = [dict(dint_R=torch.empty_like(o["dint_R"]), dsub=torch.empty_like(o["disp"]),
                  valid=torch.empty_like(o["valid"]), disp=torch.empty_like(o["disp"]))
             for o in b.outputs]
     for (plan, ref, tar), o in zip(items, outs):     # warm the per-pair path
         api.match(plan, ref, tar, out=o)
     torch.cuda.synchronize()
-    e[1].record()
+    e[2].record()
     for _ in range(n):
         for (plan, ref, tar), o in zip(items, outs):
             api.match(plan, ref, tar, out=o)
-    e[2].record()
+    e[3].record()
     torch.cuda.synchronize()
-    t_b = e[0].elapsed_time(e[1]) / n
-    t_p = e[1].elapsed_time(e[2]) / n
+    t_p = e[2].elapsed_time(e[3]) / n
     same = all(torch.equal(o["dint_R"], p["dint_R"]) for o, p in zip(b.outputs, outs))
     return dict(pairs=len(ws), elements=el, batch_ms=round(t_b, 3),
                 batch_gpd_s=round(el / (t_b / 1e3) / 1e9, 3), per_pair_ms=round(t_p, 3),

@@ -1,11 +1,12 @@
 // Batched form: many stereo pairs of uneven size and disparity range in one
-// captured graph.  The per-pair cheap stages (warp, block statistics, NCC
-// volume, left-right check) are enqueued per pair; the dominant stage, the
-// aggregation + WTA of both cost volumes of every pair, runs as one
-// persistent launch per (radius, guide type) group that takes tiles of all
-// pairs of the group from a work queue, largest disparity range first.
-// Every tile runs the same code as the per-pair path, so each pair's result
-// is bitwise the plain path's.
+// captured graph of a dozen launches.  The cheap stages (warp, block
+// statistics, NCC volume, left-right check) run as one launch per stage and
+// element type (per NCC radius) over the blocks of every pair; the dominant
+// stage, the aggregation + WTA of both cost volumes of every pair, runs as
+// one persistent launch per (radius, guide type) group that takes tiles of
+// all pairs of the group from a work queue, largest disparity range first.
+// Every block and tile runs the same code as the per-pair path, so each
+// pair's result is bitwise the plain path's.
 #include <algorithm>
 #include <cstring>
 #include <new>
@@ -26,6 +27,20 @@ struct Group {
   size_t tiles_off;           // in the workspace
 };
 
+// One batched launch of a cheap stage: its jobs (pair, and for statistics
+// which image), the block prefix, and where both live in the workspace.
+enum JobKind { JK_WARP = 0, JK_STATS = 1, JK_NCC = 2, JK_LR = 3 };
+struct JobList {
+  JobKind kind;
+  stereo_dtype dt;
+  int r;                      // NCC radius; statistics: largest radius
+  std::vector<int> pair;
+  std::vector<int> which;     // statistics: 0 = reference, 1 = warped target
+  std::vector<int> first;     // block prefix, size jobs + 1
+  size_t job_bytes;
+  size_t jobs_off, first_off;
+};
+
 __global__ void zero_u32_kernel(unsigned int* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -38,6 +53,7 @@ struct stereo_batch_s {
   std::vector<Plan> plans;             // copies of the pairs' plans
   std::vector<size_t> pair_ws;         // offset of each pair's plan workspace
   std::vector<Group> groups;
+  std::vector<JobList> lists;
   size_t desc_off = 0, desc_bytes = 0; // per-volume descriptors (2 per pair)
   size_t counter_off = 0;
   size_t ws_bytes = 0;
@@ -108,6 +124,50 @@ void build_layout(stereo_batch_s& b) {
   }
   b.counter_off = o;
   o = align256(o + sizeof(unsigned int) * std::max<size_t>(1, b.groups.size()));
+  // job lists of the cheap stages, in launch order
+  b.lists.clear();
+  auto list_of = [&](JobKind k, stereo_dtype dt, int r) -> JobList& {
+    for (JobList& L : b.lists)
+      if (L.kind == k && L.dt == dt && (k != JK_NCC || L.r == r)) return L;
+    JobList L;
+    L.kind = k; L.dt = dt; L.r = r;
+    L.job_bytes = k == JK_WARP ? sizeof(WarpJob) : k == JK_STATS ? sizeof(StatsJob)
+                : k == JK_NCC ? sizeof(NccJob) : sizeof(LrJob);
+    L.first.push_back(0);
+    b.lists.push_back(L);
+    return b.lists.back();
+  };
+  auto push = [](JobList& L, int pair, int which, int blocks) {
+    L.pair.push_back(pair);
+    L.which.push_back(which);
+    L.first.push_back(L.first.back() + blocks);
+  };
+  for (int i = 0; i < n; ++i) {
+    const Plan& P = b.plans[i];
+    push(list_of(JK_WARP, P.p.dtype, 0), i, 0, warp_job_blocks(P));
+  }
+  for (int i = 0; i < n; ++i) {
+    const Plan& P = b.plans[i];
+    JobList& Lr = list_of(JK_STATS, P.p.dtype, 0);
+    push(Lr, i, 0, stats_job_blocks(P.W, P.H, P.r));
+    Lr.r = std::max(Lr.r, P.r);
+    JobList& Lt = list_of(JK_STATS, STEREO_F32, 0);
+    push(Lt, i, 1, stats_job_blocks(P.W, P.H, P.r));
+    Lt.r = std::max(Lt.r, P.r);
+  }
+  for (int i = 0; i < n; ++i) {
+    const Plan& P = b.plans[i];
+    push(list_of(JK_NCC, P.p.dtype, P.r), i, 0, ncc_job_blocks(P, P.W + P.D - 1, 0, P.D));
+  }
+  for (int i = 0; i < n; ++i)
+    if (b.items[i].valid || b.items[i].disp)
+      push(list_of(JK_LR, STEREO_F32, 0), i, 0, lr_job_blocks(b.plans[i]));
+  for (JobList& L : b.lists) {
+    L.jobs_off = o;
+    o = align256(o + L.job_bytes * L.pair.size());
+    L.first_off = o;
+    o = align256(o + sizeof(int) * L.first.size());
+  }
   b.pair_ws.resize(n);
   for (int i = 0; i < n; ++i) {
     b.pair_ws[i] = o;
@@ -152,6 +212,45 @@ stereo_status bind(stereo_batch_s& b, void* ws, size_t bytes, hipStream_t s) {
   }
   BHIP(hipMemcpyAsync(at<char>(ws, b.desc_off), b.host_desc.data(), b.desc_bytes,
                       hipMemcpyHostToDevice, s), "upload descriptors");
+  // job descriptors of the cheap stages
+  std::vector<std::vector<char>> host_jobs(b.lists.size());
+  for (size_t li = 0; li < b.lists.size(); ++li) {
+    const JobList& L = b.lists[li];
+    std::vector<char>& hj = host_jobs[li];
+    hj.assign(L.job_bytes * L.pair.size(), 0);
+    for (size_t k = 0; k < L.pair.size(); ++k) {
+      const int i = L.pair[k];
+      const Plan& P = b.plans[i];
+      void* pws = at<char>(ws, b.pair_ws[i]);
+      float* tarw = at<float>(pws, P.off_tarw);
+      float* st = at<float>(pws, P.off_stats);
+      const size_t sn = (size_t)P.stats_w * P.H;
+      char* dst = hj.data() + k * L.job_bytes;
+      if (L.kind == JK_WARP) {
+        const WarpJob J = warp_job(P, b.items[i].tar, tarw);
+        memcpy(dst, &J, sizeof(J));
+      } else if (L.kind == JK_STATS) {
+        const StatsJob J = L.which[k] == 0
+            ? stats_job(P, b.items[i].ref, P.p.pitch_ref, st, st + sn)
+            : stats_job(P, tarw, P.W, st + 2 * sn, st + 3 * sn);
+        memcpy(dst, &J, sizeof(J));
+      } else if (L.kind == JK_NCC) {
+        const NccJob J = ncc_job(P, b.items[i].ref, tarw, st, st + sn, st + 2 * sn, st + 3 * sn,
+                                 at<float>(pws, P.off_cvol), P.W + P.D - 1, P.cw,
+                                 (int64_t)P.H * P.cw, 0, 0, P.D);
+        memcpy(dst, &J, sizeof(J));
+      } else {
+        const LrJob J = lr_job(P, b.items[i].dint_R,
+                               P.p.lr_check ? at<int16_t>(pws, P.off_dT) : nullptr,
+                               at<float>(pws, P.off_dsub), b.items[i].valid, b.items[i].disp);
+        memcpy(dst, &J, sizeof(J));
+      }
+    }
+    BHIP(hipMemcpyAsync(at<char>(ws, L.jobs_off), hj.data(), hj.size(), hipMemcpyHostToDevice,
+                        s), "upload jobs");
+    BHIP(hipMemcpyAsync(at<char>(ws, L.first_off), L.first.data(), sizeof(int) * L.first.size(),
+                        hipMemcpyHostToDevice, s), "upload job prefix");
+  }
   for (const Group& G : b.groups)
     BHIP(hipMemcpyAsync(at<char>(ws, G.tiles_off), G.tiles.data(), sizeof(int) * G.tiles.size(),
                         hipMemcpyHostToDevice, s), "upload tiles");
@@ -163,23 +262,38 @@ stereo_status bind(stereo_batch_s& b, void* ws, size_t bytes, hipStream_t s) {
 stereo_status enqueue(stereo_batch_s& b, hipStream_t s) {
   void* ws = b.bound_ws;
   BREQ(ws, "batch not bound to a workspace");
-  const int n = (int)b.items.size();
-  for (int i = 0; i < n; ++i) {
-    const Plan& P = b.plans[i];
-    void* pws = at<char>(ws, b.pair_ws[i]);
-    float* tarw = at<float>(pws, P.off_tarw);
-    float* st = at<float>(pws, P.off_stats);
-    const size_t sn = (size_t)P.stats_w * P.H;
-    BHIP(launch_warp(P, b.items[i].tar, tarw, s), "batch warp");
-    BHIP(launch_block_stats(P, b.items[i].ref, P.p.dtype, P.p.pitch_ref, st, st + sn, s),
-         "batch stats");
-    BHIP(launch_block_stats(P, tarw, STEREO_F32, P.W, st + 2 * sn, st + 3 * sn, s),
-         "batch stats");
-    BHIP(launch_ncc(P, b.items[i].ref, tarw, st, st + sn, st + 2 * sn, st + 3 * sn,
-                    at<float>(pws, P.off_cvol), P.W + P.D - 1, P.cw, (int64_t)P.H * P.cw, 0, s,
-                    0, -1, 1),
-         "batch ncc");
-  }
+  auto run_list = [&](const JobList& L) -> stereo_status {
+    const int nj = (int)L.pair.size();
+    const int blocks = L.first.back();
+    const int* first = at<int>(ws, L.first_off);
+    const void* jobs = at<char>(ws, L.jobs_off);
+    switch (L.kind) {
+      case JK_WARP:
+        BHIP(launch_warp_jobs(L.dt, static_cast<const WarpJob*>(jobs), first, nj, blocks, s),
+             "batch warp");
+        break;
+      case JK_STATS:
+        BHIP(launch_stats_jobs(L.dt, static_cast<const StatsJob*>(jobs), first, nj, blocks, L.r,
+                               s), "batch statistics");
+        break;
+      case JK_NCC:
+        BHIP(launch_ncc_jobs(L.r, L.dt, 1, static_cast<const NccJob*>(jobs), first, nj, blocks,
+                             s), "batch ncc");
+        break;
+      case JK_LR:
+        BHIP(launch_lr_jobs(static_cast<const LrJob*>(jobs), first, nj, blocks, s),
+             "batch lr check");
+        break;
+    }
+    return STEREO_OK;
+  };
+  // warp first (the target statistics read its output), then statistics, NCC
+  for (JobKind k : {JK_WARP, JK_STATS, JK_NCC})
+    for (const JobList& L : b.lists)
+      if (L.kind == k) {
+        stereo_status st = run_list(L);
+        if (st != STEREO_OK) return st;
+      }
   unsigned int* ctr = at<unsigned int>(ws, b.counter_off);
   const int ng = (int)b.groups.size();
   hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, ctr, ng);
@@ -192,14 +306,11 @@ stereo_status enqueue(stereo_batch_s& b, hipStream_t s) {
     BHIP(launch_bilateral_persistent(G.R, G.gdt, G.levels, desc, at<int>(ws, G.tiles_off), nt,
                                      ctr + g, groups, s), "batch aggregation");
   }
-  for (int i = 0; i < n; ++i) {
-    const Plan& P = b.plans[i];
-    void* pws = at<char>(ws, b.pair_ws[i]);
-    if (b.items[i].valid || b.items[i].disp)
-      BHIP(launch_lr_check(P, b.items[i].dint_R, P.p.lr_check ? at<int16_t>(pws, P.off_dT) : nullptr,
-                           at<float>(pws, P.off_dsub), b.items[i].valid, b.items[i].disp, s),
-           "batch lr check");
-  }
+  for (const JobList& L : b.lists)
+    if (L.kind == JK_LR) {
+      stereo_status st = run_list(L);
+      if (st != STEREO_OK) return st;
+    }
   return STEREO_OK;
 }
 

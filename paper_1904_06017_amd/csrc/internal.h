@@ -128,6 +128,53 @@ hipError_t launch_lr_check(const Plan& P, const int16_t* dR, const int16_t* dT,
                            const float* dsub, uint8_t* valid, float* disp,
                            hipStream_t s);
 
+// ---- batched stages: one launch covers every job of a list.  Job j owns
+// blocks [first[j], first[j+1]) of the launch (first[0] = 0, first[n] = the
+// launch's block count) and runs exactly the per-pair kernel's code on its own
+// block grid, so a batched result is bitwise the per-pair one.
+struct WarpJob {            // grid: gx = ceil(W / 256) x H rows
+  const void* tar; int64_t pitch; float* out;
+  double dp, c0, c1, c2;
+  int W, H, persp, gx;
+};
+struct StatsJob {           // grid: gx = ceil((W + 2r) / 64) x ceil(H / 16)
+  const void* img; int64_t pitch; float* z; float* isd;
+  int W, H, r, gx;
+};
+struct NccJob {             // grid: gx = ceil(out_w / 64) x gy = ceil(H / 32) x level blocks
+  const void* ref; int64_t ref_pitch; const float* tarw;
+  const float *zX, *isdX, *zY, *isdY;
+  float* C; int64_t out_pitch, out_slice;
+  int W, H, d_first, d_end, out_w, anchor, gx, gy;
+};
+struct LrJob {              // grid: gx = ceil(W / 256) x H rows
+  const int16_t* dR; const int16_t* dT; const float* dsub; uint8_t* valid; float* disp;
+  double dp, c0, c1, c2;
+  float lr_delta;
+  int W, H, use_lr, persp, gx;
+};
+int warp_job_blocks(const Plan& P);
+int stats_job_blocks(int W, int H, int r);
+int ncc_job_blocks(const Plan& P, int out_w, int d_first, int d_end);
+int lr_job_blocks(const Plan& P);
+WarpJob warp_job(const Plan& P, const void* tar, float* tar_w);
+StatsJob stats_job(const Plan& P, const void* img, int64_t pitch, float* z, float* isd);
+NccJob ncc_job(const Plan& P, const void* ref, const float* tar_w, const float* zX,
+               const float* isdX, const float* zY, const float* isdY, float* C, int out_w,
+               int64_t out_pitch, int64_t out_slice, int anchor, int d_first, int d_end);
+LrJob lr_job(const Plan& P, const int16_t* dR, const int16_t* dT, const float* dsub,
+             uint8_t* valid, float* disp);
+// jobs / first are device arrays; dt is the element type of the job images
+// (ref for the NCC); stats LDS is sized for max_r; quad as in launch_ncc.
+hipError_t launch_warp_jobs(stereo_dtype dt, const WarpJob* jobs, const int* first, int n,
+                            int blocks, hipStream_t s);
+hipError_t launch_stats_jobs(stereo_dtype dt, const StatsJob* jobs, const int* first, int n,
+                             int blocks, int max_r, hipStream_t s);
+hipError_t launch_ncc_jobs(int r, stereo_dtype dt, int quad, const NccJob* jobs,
+                           const int* first, int n, int blocks, hipStream_t s);
+hipError_t launch_lr_jobs(const LrJob* jobs, const int* first, int n, int blocks,
+                          hipStream_t s);
+
 // Grad workspace layout for the plan (sets g_off / g_end); 0 for U8 plans.
 size_t grad_layout(Plan& P, size_t base);
 

@@ -16,12 +16,10 @@ __device__ __forceinline__ float ld(const T* p) { return static_cast<float>(*p);
 // s = delta_p - d_road(x + delta_p, v).  The shift is evaluated in FP64 apart
 // from x so that the fractional position stays exact at large x.
 template <typename T>
-__global__ void __launch_bounds__(256)
-warp_kernel(const T* __restrict__ tar, int64_t pitch, int W, int H,
-            double delta_p, double c0, double c1, double c2, int persp,
-            float* __restrict__ out) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int v = blockIdx.y;
+__device__ __forceinline__ void warp_body(const T* __restrict__ tar, int64_t pitch, int W,
+                                          double delta_p, double c0, double c1, double c2,
+                                          int persp, float* __restrict__ out, int bx, int v) {
+  const int x = bx * 256 + threadIdx.x;
   if (x >= W) return;
   const T* row = tar + (int64_t)v * pitch;
   float val;
@@ -46,6 +44,14 @@ warp_kernel(const T* __restrict__ tar, int64_t pitch, int W, int H,
   out[(int64_t)v * W + x] = val;
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256)
+warp_kernel(const T* __restrict__ tar, int64_t pitch, int W, int H,
+            double delta_p, double c0, double c1, double c2, int persp,
+            float* __restrict__ out) {
+  warp_body<T>(tar, pitch, W, delta_p, c0, c1, c2, persp, out, blockIdx.x, blockIdx.y);
+}
+
 // Block statistics.  One workgroup covers 64 block centres x 16 rows; the
 // clamped input tile (16 + 2r rows x 64 + 2r columns, offset by -128) is
 // staged in LDS, then each thread forms the mean and the population
@@ -56,14 +62,14 @@ warp_kernel(const T* __restrict__ tar, int64_t pitch, int W, int H,
 constexpr int ST_TX = 64, ST_TY = 16;
 
 template <typename T>
-__global__ void __launch_bounds__(256)
-block_stats_kernel(const T* __restrict__ img, int64_t pitch, int W, int H, int r,
-                   float* __restrict__ zmap, float* __restrict__ isd) {
-  extern __shared__ float tile[];   // (ST_TY + 2r) x (ST_TX + 2r)
+__device__ __forceinline__ void block_stats_body(const T* __restrict__ img, int64_t pitch,
+                                                 int W, int H, int r, float* __restrict__ zmap,
+                                                 float* __restrict__ isd, float* tile, int bx,
+                                                 int by) {
   const int SW = W + 2 * r;
   const int tw = ST_TX + 2 * r, th = ST_TY + 2 * r;
-  const int xc0 = blockIdx.x * ST_TX - r;    // first block centre (image col)
-  const int y0 = blockIdx.y * ST_TY;
+  const int xc0 = bx * ST_TX - r;            // first block centre (image col)
+  const int y0 = by * ST_TY;
   for (int i = threadIdx.x; i < tw * th; i += blockDim.x) {
     const int yy = i / tw, xx = i - yy * tw;
     const int gy = min(max(y0 - r + yy, 0), H - 1);
@@ -75,7 +81,7 @@ block_stats_kernel(const T* __restrict__ img, int64_t pitch, int W, int H, int r
   const float inv_n = 1.0f / (float)n;
   for (int o = threadIdx.x; o < ST_TX * ST_TY; o += blockDim.x) {
     const int ty = o / ST_TX, tx = o - ty * ST_TX;
-    const int xi = blockIdx.x * ST_TX + tx;       // map column index
+    const int xi = bx * ST_TX + tx;               // map column index
     const int y = y0 + ty;
     if (xi >= SW || y >= H) continue;
     float s = 0.0f;
@@ -93,6 +99,14 @@ block_stats_kernel(const T* __restrict__ img, int64_t pitch, int W, int H, int r
     zmap[(int64_t)y * SW + xi] = m * is;
     isd[(int64_t)y * SW + xi] = is;
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+block_stats_kernel(const T* __restrict__ img, int64_t pitch, int W, int H, int r,
+                   float* __restrict__ zmap, float* __restrict__ isd) {
+  extern __shared__ float tile[];   // (ST_TY + 2r) x (ST_TX + 2r)
+  block_stats_body<T>(img, pitch, W, H, r, zmap, isd, tile, blockIdx.x, blockIdx.y);
 }
 
 // NCC cost, Eq. (8), in its equivalent 1 - NCC form on offset intensities:
@@ -123,21 +137,23 @@ struct NccGeom {
 // inside the last quad are written as 0), QUAD = 0 the planar layout
 // [levels][H][pitch].
 template <int r, typename T, int QUAD>
-__global__ void __launch_bounds__(256)
-ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
-           const float* __restrict__ tarw, int W, int H, int d_first, int d_end,
-           const float* __restrict__ zX, const float* __restrict__ isdX,
-           const float* __restrict__ zY, const float* __restrict__ isdY,
-           float* __restrict__ C, int out_w, int64_t out_pitch,
-           int64_t out_slice, int anchor) {
+__device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_pitch,
+                                         const float* __restrict__ tarw, int W, int H,
+                                         int d_first, int d_end,
+                                         const float* __restrict__ zX,
+                                         const float* __restrict__ isdX,
+                                         const float* __restrict__ zY,
+                                         const float* __restrict__ isdY,
+                                         float* __restrict__ C, int out_w, int64_t out_pitch,
+                                         int64_t out_slice, int anchor, float* sm, int bx,
+                                         int by, int bz) {
   using G = NccGeom<r>;
   constexpr int K = G::K;
-  extern __shared__ float sm[];
   float* As = sm;                         // [ROWS][AW]
   float* Bs = sm + G::ROWS * G::AW;       // [ROWS][BW]
-  const int x0 = blockIdx.x * NC_TX;
-  const int y0 = blockIdx.y * NC_TY;
-  const int d0 = d_first + blockIdx.z * NC_DC;
+  const int x0 = bx * NC_TX;
+  const int y0 = by * NC_TY;
+  const int d0 = d_first + bz * NC_DC;
   const int SW = W + 2 * r;
   // image column of A[.][0] and B[.][0]
   //   anchor 0: A = X' at x + j - r, B = Y' at x - d + j - r
@@ -225,6 +241,66 @@ ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
   }
 }
 
+template <int r, typename T, int QUAD>
+__global__ void __launch_bounds__(256)
+ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
+           const float* __restrict__ tarw, int W, int H, int d_first, int d_end,
+           const float* __restrict__ zX, const float* __restrict__ isdX,
+           const float* __restrict__ zY, const float* __restrict__ isdY,
+           float* __restrict__ C, int out_w, int64_t out_pitch,
+           int64_t out_slice, int anchor) {
+  extern __shared__ float sm[];
+  ncc_body<r, T, QUAD>(ref, ref_pitch, tarw, W, H, d_first, d_end, zX, isdX, zY, isdY, C,
+                       out_w, out_pitch, out_slice, anchor, sm, blockIdx.x, blockIdx.y,
+                       blockIdx.z);
+}
+
+
+// Job index of a block of a batched launch (binary search of the prefix).
+__device__ __forceinline__ int job_of(const int* __restrict__ first, int n, int b) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+warp_jobs_kernel(const WarpJob* __restrict__ jobs, const int* __restrict__ first, int n) {
+  const int j = job_of(first, n, blockIdx.x);
+  const WarpJob& J = jobs[j];
+  const int l = blockIdx.x - first[j];
+  warp_body<T>(static_cast<const T*>(J.tar), J.pitch, J.W, J.dp, J.c0, J.c1, J.c2, J.persp,
+               J.out, l % J.gx, l / J.gx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+stats_jobs_kernel(const StatsJob* __restrict__ jobs, const int* __restrict__ first, int n) {
+  extern __shared__ float tile[];
+  const int j = job_of(first, n, blockIdx.x);
+  const StatsJob& J = jobs[j];
+  const int l = blockIdx.x - first[j];
+  block_stats_body<T>(static_cast<const T*>(J.img), J.pitch, J.W, J.H, J.r, J.z, J.isd, tile,
+                      l % J.gx, l / J.gx);
+}
+
+template <int r, typename T, int QUAD>
+__global__ void __launch_bounds__(256)
+ncc_jobs_kernel(const NccJob* __restrict__ jobs, const int* __restrict__ first, int n) {
+  extern __shared__ float sm[];
+  const int j = job_of(first, n, blockIdx.x);
+  const NccJob& J = jobs[j];
+  const int l = blockIdx.x - first[j];
+  const int gxy = J.gx * J.gy;
+  const int bz = l / gxy, rem = l - bz * gxy;
+  ncc_body<r, T, QUAD>(static_cast<const T*>(J.ref), J.ref_pitch, J.tarw, J.W, J.H, J.d_first,
+                       J.d_end, J.zX, J.isdX, J.zY, J.isdY, J.C, J.out_w, J.out_pitch,
+                       J.out_slice, J.anchor, sm, rem % J.gx, rem / J.gx, bz);
+}
+
 template <int r, typename T>
 hipError_t launch_ncc_r(const Plan& P, const T* ref, const float* tar_w, const float* zX,
                         const float* isdX, const float* zY, const float* isdY, float* C,
@@ -260,6 +336,103 @@ hipError_t launch_ncc_t(const Plan& P, const T* ref, const float* tar_w, const f
 }
 
 }  // namespace
+
+int warp_job_blocks(const Plan& P) { return ((P.W + 255) / 256) * P.H; }
+int stats_job_blocks(int W, int H, int r) {
+  return ((W + 2 * r + ST_TX - 1) / ST_TX) * ((H + ST_TY - 1) / ST_TY);
+}
+int ncc_job_blocks(const Plan& P, int out_w, int d_first, int d_end) {
+  return ((out_w + NC_TX - 1) / NC_TX) * ((P.H + NC_TY - 1) / NC_TY) *
+         ((d_end - d_first + NC_DC - 1) / NC_DC);
+}
+
+WarpJob warp_job(const Plan& P, const void* tar, float* tar_w) {
+  const stereo_params& p = P.p;
+  WarpJob J{};
+  J.tar = tar; J.pitch = p.pitch_tar; J.out = tar_w;
+  J.dp = p.perspective ? (double)p.delta_p : 0.0;
+  J.c0 = p.plane[0]; J.c1 = p.plane[1]; J.c2 = p.plane[2];
+  J.W = P.W; J.H = P.H; J.persp = p.perspective; J.gx = (P.W + 255) / 256;
+  return J;
+}
+
+StatsJob stats_job(const Plan& P, const void* img, int64_t pitch, float* z, float* isd) {
+  StatsJob J{};
+  J.img = img; J.pitch = pitch; J.z = z; J.isd = isd;
+  J.W = P.W; J.H = P.H; J.r = P.r; J.gx = (P.W + 2 * P.r + ST_TX - 1) / ST_TX;
+  return J;
+}
+
+NccJob ncc_job(const Plan& P, const void* ref, const float* tar_w, const float* zX,
+               const float* isdX, const float* zY, const float* isdY, float* C, int out_w,
+               int64_t out_pitch, int64_t out_slice, int anchor, int d_first, int d_end) {
+  NccJob J{};
+  J.ref = ref; J.ref_pitch = P.p.pitch_ref; J.tarw = tar_w;
+  J.zX = zX; J.isdX = isdX; J.zY = zY; J.isdY = isdY;
+  J.C = C; J.out_pitch = out_pitch; J.out_slice = out_slice;
+  J.W = P.W; J.H = P.H; J.d_first = d_first; J.d_end = d_end < 0 ? P.D : d_end;
+  J.out_w = out_w; J.anchor = anchor;
+  J.gx = (out_w + NC_TX - 1) / NC_TX; J.gy = (P.H + NC_TY - 1) / NC_TY;
+  return J;
+}
+
+hipError_t launch_warp_jobs(stereo_dtype dt, const WarpJob* jobs, const int* first, int n,
+                            int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (dt == STEREO_U8)
+    hipLaunchKernelGGL(warp_jobs_kernel<uint8_t>, dim3(blocks), dim3(256), 0, s, jobs, first, n);
+  else
+    hipLaunchKernelGGL(warp_jobs_kernel<float>, dim3(blocks), dim3(256), 0, s, jobs, first, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_jobs(stereo_dtype dt, const StatsJob* jobs, const int* first, int n,
+                             int blocks, int max_r, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  const size_t lds = sizeof(float) * (ST_TX + 2 * max_r) * (ST_TY + 2 * max_r);
+  if (dt == STEREO_U8)
+    hipLaunchKernelGGL(stats_jobs_kernel<uint8_t>, dim3(blocks), dim3(256), lds, s, jobs, first,
+                       n);
+  else
+    hipLaunchKernelGGL(stats_jobs_kernel<float>, dim3(blocks), dim3(256), lds, s, jobs, first, n);
+  return hipGetLastError();
+}
+
+namespace {
+template <int r, typename T>
+hipError_t ncc_jobs_r(int quad, const NccJob* jobs, const int* first, int n, int blocks,
+                      hipStream_t s) {
+  if (quad)
+    hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 1>), dim3(blocks), dim3(256),
+                       NccGeom<r>::lds_bytes, s, jobs, first, n);
+  else
+    hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 0>), dim3(blocks), dim3(256),
+                       NccGeom<r>::lds_bytes, s, jobs, first, n);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t ncc_jobs_t(int r, int quad, const NccJob* jobs, const int* first, int n, int blocks,
+                      hipStream_t s) {
+  switch (r) {
+    case 1: return ncc_jobs_r<1, T>(quad, jobs, first, n, blocks, s);
+    case 2: return ncc_jobs_r<2, T>(quad, jobs, first, n, blocks, s);
+    case 3: return ncc_jobs_r<3, T>(quad, jobs, first, n, blocks, s);
+    case 4: return ncc_jobs_r<4, T>(quad, jobs, first, n, blocks, s);
+    case 5: return ncc_jobs_r<5, T>(quad, jobs, first, n, blocks, s);
+    case 6: return ncc_jobs_r<6, T>(quad, jobs, first, n, blocks, s);
+    case 7: return ncc_jobs_r<7, T>(quad, jobs, first, n, blocks, s);
+    case 8: return ncc_jobs_r<8, T>(quad, jobs, first, n, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace
+
+hipError_t launch_ncc_jobs(int r, stereo_dtype dt, int quad, const NccJob* jobs,
+                           const int* first, int n, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (dt == STEREO_U8) return ncc_jobs_t<uint8_t>(r, quad, jobs, first, n, blocks, s);
+  return ncc_jobs_t<float>(r, quad, jobs, first, n, blocks, s);
+}
 
 hipError_t launch_warp(const Plan& P, const void* tar, float* tar_w, hipStream_t s) {
   dim3 grid((P.W + 255) / 256, P.H);

@@ -36,13 +36,13 @@ wta_kernel(const float* __restrict__ E, int W, int H, int D,
 
 // valid = (u - dR >= 0) && (dR - dT(u - dR))^2 <= delta_r;
 // disp = l - delta_p + d_road(u - l + delta_p, v), evaluated in FP64.
-__global__ void __launch_bounds__(256)
-lr_kernel(const int16_t* __restrict__ dR, const int16_t* __restrict__ dT,
-          const float* __restrict__ dsub, int W, int H, float lr_delta,
-          int use_lr, int persp, double delta_p, double c0, double c1, double c2,
-          uint8_t* __restrict__ valid, float* __restrict__ disp) {
-  const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  const int v = blockIdx.y;
+__device__ __forceinline__ void lr_body(const int16_t* __restrict__ dR,
+                                        const int16_t* __restrict__ dT,
+                                        const float* __restrict__ dsub, int W, float lr_delta,
+                                        int use_lr, int persp, double delta_p, double c0,
+                                        double c1, double c2, uint8_t* __restrict__ valid,
+                                        float* __restrict__ disp, int bx, int v) {
+  const int u = bx * 256 + threadIdx.x;
   if (u >= W) return;
   const int64_t p = (int64_t)v * W + u;
   const int d = dR[p];
@@ -61,6 +61,33 @@ lr_kernel(const int16_t* __restrict__ dR, const int16_t* __restrict__ dT,
   }
 }
 
+__global__ void __launch_bounds__(256)
+lr_kernel(const int16_t* __restrict__ dR, const int16_t* __restrict__ dT,
+          const float* __restrict__ dsub, int W, int H, float lr_delta,
+          int use_lr, int persp, double delta_p, double c0, double c1, double c2,
+          uint8_t* __restrict__ valid, float* __restrict__ disp) {
+  lr_body(dR, dT, dsub, W, lr_delta, use_lr, persp, delta_p, c0, c1, c2, valid, disp,
+          blockIdx.x, blockIdx.y);
+}
+
+__device__ __forceinline__ int job_of(const int* __restrict__ first, int n, int b) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(256)
+lr_jobs_kernel(const LrJob* __restrict__ jobs, const int* __restrict__ first, int n) {
+  const int j = job_of(first, n, blockIdx.x);
+  const LrJob& J = jobs[j];
+  const int l = blockIdx.x - first[j];
+  lr_body(J.dR, J.dT, J.dsub, J.W, J.lr_delta, J.use_lr, J.persp, J.dp, J.c0, J.c1, J.c2,
+          J.valid, J.disp, l % J.gx, l / J.gx);
+}
+
 }  // namespace
 
 hipError_t launch_wta(const Plan& P, const float* E, int16_t* dint, float* dsub,
@@ -68,6 +95,28 @@ hipError_t launch_wta(const Plan& P, const float* E, int16_t* dint, float* dsub,
   const int64_t HW = (int64_t)P.W * P.H;
   hipLaunchKernelGGL(wta_kernel, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, s,
                      E, P.W, P.H, P.D, dint, dsub);
+  return hipGetLastError();
+}
+
+int lr_job_blocks(const Plan& P) { return ((P.W + 255) / 256) * P.H; }
+
+LrJob lr_job(const Plan& P, const int16_t* dR, const int16_t* dT, const float* dsub,
+             uint8_t* valid, float* disp) {
+  const stereo_params& p = P.p;
+  LrJob J{};
+  J.dR = dR; J.dT = dT; J.dsub = dsub; J.valid = valid; J.disp = disp;
+  J.dp = p.perspective ? (double)p.delta_p : 0.0;
+  J.c0 = p.plane[0]; J.c1 = p.plane[1]; J.c2 = p.plane[2];
+  J.lr_delta = p.lr_delta;
+  J.W = P.W; J.H = P.H; J.use_lr = (p.lr_check && dT) ? 1 : 0; J.persp = p.perspective;
+  J.gx = (P.W + 255) / 256;
+  return J;
+}
+
+hipError_t launch_lr_jobs(const LrJob* jobs, const int* first, int n, int blocks,
+                          hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lr_jobs_kernel, dim3(blocks), dim3(256), 0, s, jobs, first, n);
   return hipGetLastError();
 }
 
