@@ -69,6 +69,15 @@ struct BilOut {
   float* disp;                      // mode 2: shifted back
   float invT;
   double delta_p, c0, c1, c2;
+  // modes 5, 6
+  const float* gD;                  // mode 5: dL / d(shifted disparity)
+  const float* cpix;                // mode 6: cost tile at the pixel
+  float* aP;                        // mode 5
+  float* A1;                        // mode 5
+  float* A2;                        // mode 6
+  float* Wp;                        // mode 5 (nullable)
+  int d_first;
+  float one_minus_c1;
 };
 
 // Everything one tile needs to know about its pair.
@@ -125,7 +134,10 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
 #pragma unroll
   for (int j = 0; j <= 2 * R; ++j) sx[j] = -(float)((j - R) * (j - R)) * ks2;
 
-  constexpr bool NORM = (MODE == 0 || MODE == 2);   // needs sum_q w(p, q)
+  constexpr bool NORM = (MODE == 0 || MODE == 2 || MODE == 5);   // needs sum_q w(p, q)
+  // modes 5, 6 also accumulate with the second weight w(p, q) (G'(p) - G'(q))
+  constexpr bool TWO = (MODE == 5 || MODE == 6);
+  constexpr int PX2 = TWO ? PX : 1, DC2 = TWO ? DC : 1;
   float wsum[PX];
   float rinv[PX];
 #pragma unroll
@@ -142,6 +154,21 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
     m2[k] = -3.402823466e38f; Zs[k] = 0.0f; S1[k] = 0.0f;
   }
   const float zscale = -o.invT * 1.4426950408889634f;
+  // modes 5, 6: per-pixel state of the softmax adjoint and the two running sums
+  float sbase[PX2], sgp[PX2], sdh[PX2], sa[PX2], sb[PX2];
+#pragma unroll
+  for (int k = 0; k < PX2; ++k) {
+    sbase[k] = 0.0f; sgp[k] = 0.0f; sdh[k] = 0.0f; sa[k] = 0.0f; sb[k] = 0.0f;
+    if (MODE == 5) {
+      const int px = x0 + tx * PX + k, py = y0 + ty;
+      if (py < H && px < W) {
+        const int64_t pix = (int64_t)py * W + px;
+        sbase[k] = -(o.sm_m[pix] + o.sm_logZ[pix]);
+        sgp[k] = o.gD[pix] * o.one_minus_c1 * (-o.invT);
+        sdh[k] = o.sm_dh[pix];
+      }
+    }
+  }
 
   // element step from level d to d + 1 (the target volume also moves one
   // column to the right per level)
@@ -219,10 +246,15 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
     __syncthreads();
 
     float acc[PX][DC];
+    float acc2[PX2][DC2];
 #pragma unroll
     for (int k = 0; k < PX; ++k)
 #pragma unroll
       for (int j = 0; j < DC; ++j) acc[k][j] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PX2; ++k)
+#pragma unroll
+      for (int j = 0; j < DC2; ++j) acc2[k][j] = 0.0f;
     const bool first = (d0 == 0);
 
     for (int dy = 0; dy <= 2 * R; ++dy) {
@@ -233,6 +265,7 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
       // weights of this tap row first: the exponentials are independent of
       // each other and of the cost reads below
       float wr[PX][2 * R + 1];
+      float wg[PX2][TWO ? 2 * R + 1 : 1];
 #pragma unroll
       for (int xx = 0; xx < PX + 2 * R; ++xx) {
         const float gq = grow[xx];
@@ -242,6 +275,7 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
           if (dx < 0 || dx > 2 * R) continue;
           const float g = gp[k] - gq;
           wr[k][dx] = __builtin_amdgcn_exp2f(fmaf(-g, g, sy + sx[dx]));
+          if constexpr (TWO) wg[k][dx] = wr[k][dx] * g;
         }
       }
       if (NORM && first) {
@@ -265,6 +299,11 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
           const float w = wr[k][dx];
 #pragma unroll
           for (int j = 0; j < DC; ++j) acc[k][j] = fmaf(w, cv[j], acc[k][j]);
+          if constexpr (TWO) {
+            const float w2 = wg[k][dx];
+#pragma unroll
+            for (int j = 0; j < DC; ++j) acc2[k][j] = fmaf(w2, cv[j], acc2[k][j]);
+          }
         }
       }
     }
@@ -286,6 +325,33 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
             const int d = d0 + j;
             if (d < D) o.E[((int64_t)d * H + py) * W + px] = MODE == 0 ? acc[k][j] * rinv[k]
                                                                        : acc[k][j];
+          }
+        }
+      } else if constexpr (MODE == 5) {
+        // softmax adjoint: P = exp(-E/T - m - log Z), dE = g' (-1/T) P (d - dh)
+        const bool in = py < H && px < W;
+#pragma unroll
+        for (int j = 0; j < DC; ++j) {
+          const int d = d0 + j;
+          if (d < D) {
+            const float e = acc[k][j] * rinv[k];
+            const float P = __builtin_amdgcn_exp2f(fmaf(-e, o.invT, sbase[k]) *
+                                                   1.4426950408889634f);
+            const float dE = sgp[k] * P * ((float)(o.d_first + d) - sdh[k]);
+            if (in) o.E[((int64_t)d * H + py) * W + px] = dE * rinv[k];
+            sa[k] = fmaf(dE, e, sa[k]);
+            sb[k] = fmaf(dE, acc2[k][j], sb[k]);
+          }
+        }
+      } else if constexpr (MODE == 6) {
+        const bool in = py < H && px < W;
+#pragma unroll
+        for (int j = 0; j < DC; ++j) {
+          const int d = d0 + j;
+          if (d < D && in) {
+            const int64_t oi = ((int64_t)d * H + py) * W + px;
+            o.E[oi] = acc[k][j];
+            sb[k] = fmaf(o.cpix[oi], acc2[k][j], sb[k]);
           }
         }
       } else if (MODE == 2) {
@@ -323,6 +389,26 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
       }
     }
     __syncthreads();
+  }
+
+  if constexpr (TWO) {
+    // the second weight carries the guide difference scaled by sqrt(kr2)
+    const float inv_kr = 1.0f / kr;
+    const int py = y0 + ty;
+#pragma unroll
+    for (int k = 0; k < PX2; ++k) {
+      const int px = x0 + tx * PX + k;
+      if (py < H && px < W) {
+        const int64_t pix = (int64_t)py * W + px;
+        if (MODE == 5) {
+          o.aP[pix] += sa[k];
+          o.A1[pix] += sb[k] * inv_kr;
+          if (o.Wp) o.Wp[pix] = wsum[k];
+        } else {
+          o.A2[pix] += -sb[k] * inv_kr;
+        }
+      }
+    }
   }
 
   if (MODE == 2) {
@@ -409,6 +495,9 @@ inline BilPair make_pair(const Plan& P, const BilArgs& a) {
   o.invT = 1.0f / P.p.softargmin_T;
   o.delta_p = P.p.perspective ? (double)P.p.delta_p : 0.0;
   o.c0 = a.plane[0]; o.c1 = a.plane[1]; o.c2 = a.plane[2];
+  o.gD = a.gD; o.cpix = a.cpix; o.aP = a.aP; o.A1 = a.A1; o.A2 = a.A2; o.Wp = a.Wp;
+  o.d_first = a.d_first;
+  o.one_minus_c1 = (float)(1.0 - a.plane[1]);
   return b;
 }
 
@@ -455,6 +544,12 @@ hipError_t launch_rdg(const Plan& P, const BilArgs& a, int mode, hipStream_t s) 
     case 1: return launch_one<R, PX, DC, TYT, GT, 1>(P, a, s);
     case 2: return launch_one<R, PX, DC, TYT, GT, 2>(P, a, s);
     case 4: return launch_one<R, PX, DC, TYT, GT, 4>(P, a, s);
+    case 5:
+    case 6:
+      if constexpr (std::is_same<GT, float>::value)
+        return mode == 5 ? launch_one<R, PX, DC, TYT, GT, 5>(P, a, s)
+                         : launch_one<R, PX, DC, TYT, GT, 6>(P, a, s);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }

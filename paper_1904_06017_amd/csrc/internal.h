@@ -49,7 +49,7 @@ enum GradRegion {
   GR_WP, GR_AP, GR_A1, GR_A2,
   GR_SUMS,                                      // [3][H][W]: alpha muY, beta, beta muX
   GR_GX, GR_GTARW,
-  GR_CT, GR_ET, GR_GET, GR_GT, GR_GCT, GR_FA,   // GR_FA: [4][DT][H][W] alpha maps
+  GR_CT, GR_GT, GR_GCT, GR_FA,                 // GR_FA: [4][DT][H][W] alpha maps
   GR_BA,                                        // [4][DT][HV][WVX] boxes
   GR_BS,                                        // [3][HV][WVX] boxes of the sums
   GR_GXV, GR_GYV, GR_GTARFIX, GR_PART_A, GR_PART_B, GR_SCRATCH, GR_COUNT
@@ -103,11 +103,22 @@ struct BilArgs {
   float* disp;
   double plane[3];    // mode 2: plane of the shift back
   int levels;         // number of levels in C (0: plan D)
+  // modes 5, 6 (backward of the soft-argmin head over one level tile):
+  const float* gD;    // mode 5: gradient of the shifted soft disparity [H][W]
+  const float* cpix;  // mode 6: the tile's cost volume (planar, as C of mode 5)
+  float* aP;          // mode 5: += sum_d dE E            [H][W]
+  float* A1;          // mode 5: += sum_q w (G(p)-G(q)) sum_d dE(p,d) C(q,d)
+  float* A2;          // mode 6: += sum_q w (G(q)-G(p)) sum_d dE(q,d)/W_q C(p,d)
+  float* Wp;          // mode 5 (nullable): sum_q w(p, q)
+  int d_first;        // modes 5, 6: level of the tile's first slice
 };
 // mode 0: write the normalised aggregated volume; mode 1: fused WTA and
 // sub-pixel refinement (the volume never leaves the chip); mode 2: fused
 // soft-argmin (soft level, softmax state, shifted disparity); mode 4: the
-// unnormalised weighted sum sum_q w(p, q) C(q, d) (adjoint gather).
+// unnormalised weighted sum sum_q w(p, q) C(q, d) (adjoint gather); modes 5
+// and 6: the two passes of the soft-argmin backward per level tile (mode 5:
+// E, the softmax adjoint dE, E out = dE / W_p, aP and A1; mode 6 on C = dE/W:
+// E out = dC = sum_q w C, and A2), float guides only.
 hipError_t launch_bilateral(const Plan& P, const BilArgs& a, int mode,
                             hipStream_t s);
 

@@ -36,135 +36,6 @@ __device__ __forceinline__ void fix_add(unsigned long long* dst, double v) {
   atomicAdd(dst, (unsigned long long)(long long)llrint(v * kFix));
 }
 
-// ---------------------------------------------------------------------------
-// sum_q w(p, q) over the window truncated to the image (Eq. 11 denominator)
-template <typename GT>
-__global__ void __launch_bounds__(kT)
-weight_sum_kernel(const GT* __restrict__ g, int64_t gp, int W, int H, int R, float ks2,
-                  float kr2, float* __restrict__ Wp) {
-  const int x = blockIdx.x * kT + threadIdx.x, y = blockIdx.y;
-  if (x >= W) return;
-  const float gpx = ldf(g + (int64_t)y * gp + x);
-  float s = 0.0f;
-  for (int dy = -R; dy <= R; ++dy) {
-    const int qy = y + dy;
-    if (qy < 0 || qy >= H) continue;
-    for (int dx = -R; dx <= R; ++dx) {
-      const int qx = x + dx;
-      if (qx < 0 || qx >= W) continue;
-      const float dg = gpx - ldf(g + (int64_t)qy * gp + qx);
-      s += __builtin_amdgcn_exp2f(-(float)(dx * dx + dy * dy) * ks2 - dg * dg * kr2);
-    }
-  }
-  Wp[(int64_t)y * W + x] = s;
-}
-
-// ---------------------------------------------------------------------------
-// soft-argmin adjoint for one level tile:
-//   P = exp(-E/T - m - logZ);  dE = g' (-1/T) P (d - dh);  g' = gD (1 - c1)
-//   writes dE and dE / W_p; accumulates a_p += sum_d dE E (tile order fixed)
-__global__ void __launch_bounds__(kT)
-soft_grad_e_kernel(const float* __restrict__ Et, const float* __restrict__ sm_m,
-                   const float* __restrict__ sm_logZ, const float* __restrict__ sm_dh,
-                   const float* __restrict__ gD, const float* __restrict__ Wp, int W,
-                   int H, int d_first, int nlev, float invT, float one_minus_c1,
-                   float* __restrict__ gE, float* __restrict__ G, float* __restrict__ aP) {
-  const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
-  const int64_t HW = (int64_t)W * H;
-  if (p >= HW) return;
-  const float l2e = 1.4426950408889634f;
-  const float base = -(sm_m[p] + sm_logZ[p]);
-  const float gp = gD[p] * one_minus_c1 * (-invT);
-  const float dh = sm_dh[p];
-  const float rw = 1.0f / Wp[p];
-  float a = aP[p];
-  for (int t = 0; t < nlev; ++t) {
-    const float e = Et[t * HW + p];
-    const float P = __builtin_amdgcn_exp2f((fmaf(-e, invT, base)) * l2e);
-    const float g = gp * P * ((float)(d_first + t) - dh);
-    gE[t * HW + p] = g;
-    G[t * HW + p] = g * rw;
-    a = fmaf(g, e, a);
-  }
-  aP[p] = a;
-}
-
-// ---------------------------------------------------------------------------
-// Guide (reference image) gradient of the aggregation weights, one level tile:
-//   A1(x) += sum_q w(x,q) (G(x) - G(q)) sum_d dE(x,d) C(q,d)
-//   A2(x) += sum_q w(x,q) (G(q) - G(x)) / W_q sum_d dE(q,d) C(x,d)
-// (q over the window of x inside the image, d over the tile).  One thread
-// per pixel, 16 x 16 pixel tiles; the halo of C, dE (4 levels per quad), G
-// and 1/W is staged in LDS per quad of levels.
-constexpr int GG_T = 16;
-
-template <int R, typename GT>
-__global__ void __launch_bounds__(kT)
-guide_grad_kernel(const float* __restrict__ Ct, const float* __restrict__ gEt,
-                  const GT* __restrict__ g, int64_t gpitch, const float* __restrict__ Wp,
-                  int W, int H, int nlev, float ks2, float kr2, float* __restrict__ A1,
-                  float* __restrict__ A2) {
-  constexpr int HX = GG_T + 2 * R;
-  __shared__ float4 Cs[HX * HX];
-  __shared__ float4 Es[HX * HX];
-  __shared__ float Gs[HX * HX];
-  __shared__ float RWs[HX * HX];
-  const int t = threadIdx.x;
-  const int tx = t % GG_T, ty = t / GG_T;
-  const int x0 = blockIdx.x * GG_T, y0 = blockIdx.y * GG_T;
-  const int x = x0 + tx, y = y0 + ty;
-  const int64_t HW = (int64_t)W * H;
-  for (int i = t; i < HX * HX; i += kT) {
-    const int yy = i / HX, xx = i - yy * HX;
-    const int gy = y0 - R + yy, gx = x0 - R + xx;
-    const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-    Gs[i] = in ? ldf(g + (int64_t)gy * gpitch + gx) : 0.0f;
-    RWs[i] = in ? 1.0f / Wp[(int64_t)gy * W + gx] : 0.0f;
-  }
-  const bool me = x < W && y < H;
-  float a1 = 0.0f, a2 = 0.0f;
-  for (int q0 = 0; q0 < nlev; q0 += 4) {
-    __syncthreads();
-    for (int i = t; i < HX * HX; i += kT) {
-      const int yy = i / HX, xx = i - yy * HX;
-      const int gy = y0 - R + yy, gx = x0 - R + xx;
-      float4 c = make_float4(0.f, 0.f, 0.f, 0.f), e = c;
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-        const int64_t o = (int64_t)gy * W + gx;
-        if (q0 + 0 < nlev) { c.x = Ct[(q0 + 0) * HW + o]; e.x = gEt[(q0 + 0) * HW + o]; }
-        if (q0 + 1 < nlev) { c.y = Ct[(q0 + 1) * HW + o]; e.y = gEt[(q0 + 1) * HW + o]; }
-        if (q0 + 2 < nlev) { c.z = Ct[(q0 + 2) * HW + o]; e.z = gEt[(q0 + 2) * HW + o]; }
-        if (q0 + 3 < nlev) { c.w = Ct[(q0 + 3) * HW + o]; e.w = gEt[(q0 + 3) * HW + o]; }
-      }
-      Cs[i] = c;
-      Es[i] = e;
-    }
-    __syncthreads();
-    if (!me) continue;
-    const int ci = (ty + R) * HX + tx + R;
-    const float4 cx = Cs[ci], ex = Es[ci];
-    const float gx = Gs[ci];
-    for (int dy = -R; dy <= R; ++dy) {
-      if (y + dy < 0 || y + dy >= H) continue;
-      for (int dx = -R; dx <= R; ++dx) {
-        if (x + dx < 0 || x + dx >= W) continue;
-        const int qi = ci + dy * HX + dx;
-        const float dg = gx - Gs[qi];
-        const float w = __builtin_amdgcn_exp2f(-(float)(dx * dx + dy * dy) * ks2 - dg * dg * kr2);
-        const float4 cq = Cs[qi], eq = Es[qi];
-        const float dot1 = ex.x * cq.x + ex.y * cq.y + ex.z * cq.z + ex.w * cq.w;
-        const float dot2 = eq.x * cx.x + eq.y * cx.y + eq.z * cx.z + eq.w * cx.w;
-        a1 = fmaf(w * dg, dot1, a1);
-        a2 = fmaf(-w * dg * RWs[qi], dot2, a2);
-      }
-    }
-  }
-  if (me) {
-    A1[(int64_t)y * W + x] += a1;
-    A2[(int64_t)y * W + x] += a2;
-  }
-}
-
 // After all tiles: B1(x) = sum_q w (G(x) - G(q)), B2(x) = sum_q w (G(q) - G(x)) a_q / W_q,
 // dG(x) = 2/sigma_r^2 [ -(A1 - a_x B1) / W_x + (A2 - B2) ];  out = gX + dG.
 template <typename GT>
@@ -616,27 +487,6 @@ stereo_status zero_f(float* p, int64_t n, hipStream_t s) {
   return STEREO_OK;
 }
 
-template <int R>
-stereo_status guide_grad_r(const Plan& P, const float* Ct, const float* gEt, const float* ref,
-                           const float* Wp, int nlev, float ks2, float kr2, float* A1, float* A2,
-                           hipStream_t s) {
-  dim3 grid((P.W + 15) / 16, (P.H + 15) / 16);
-  LAUNCH("guide gradient", (guide_grad_kernel<R, float>), grid, dim3(256), 0, s, Ct, gEt, ref,
-         P.p.pitch_ref, Wp, P.W, P.H, nlev, ks2, kr2, A1, A2);
-  return STEREO_OK;
-}
-
-stereo_status guide_grad(const Plan& P, const float* Ct, const float* gEt, const float* ref,
-                         const float* Wp, int nlev, float ks2, float kr2, float* A1, float* A2,
-                         hipStream_t s) {
-  switch (P.R) {
-#define GG_CASE(R_) case R_: return guide_grad_r<R_>(P, Ct, gEt, ref, Wp, nlev, ks2, kr2, A1, A2, s);
-    GG_CASE(1) GG_CASE(2) GG_CASE(3) GG_CASE(4) GG_CASE(5) GG_CASE(6) GG_CASE(7) GG_CASE(8)
-#undef GG_CASE
-    default: return fail(STEREO_ERR_UNSUPPORTED, "bil_radius");
-  }
-}
-
 template <int r>
 stereo_status box_r(const Plan& P, const float* F, int nmaps, float* B, hipStream_t s) {
   dim3 grid((P.W + 2 * r + 63) / 64, (P.H + 2 * r + 31) / 32, nmaps);
@@ -717,7 +567,7 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
   // the three level sums are one [3][H][W] region: one box launch covers them
   float *SamY = R_(GR_SUMS), *Sb = SamY + HW, *SbmX = SamY + 2 * HW;
   float *gX = R_(GR_GX), *gtarw = R_(GR_GTARW);
-  float *Ct = R_(GR_CT), *Et = R_(GR_ET), *gEt = R_(GR_GET), *Gt = R_(GR_GT), *gCt = R_(GR_GCT);
+  float *Ct = R_(GR_CT), *Gt = R_(GR_GT), *gCt = R_(GR_GCT);
   float* Fa = R_(GR_FA);
   float *FamX = Fa + DT * HW, *Fg = Fa + 2 * DT * HW, *FgmY = Fa + 3 * DT * HW;
   float* Ba = R_(GR_BA);
@@ -743,35 +593,37 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
   if ((st = zero_f(gYv, (int64_t)HV * WVY, stream)) != STEREO_OK) return st;
   LAUNCH("zero", zero_u64_kernel, flat, dim3(256), 0, stream, gfix, HW);
 
-  // forward state that is cheap to rebuild: warp, block statistics, weight sums
+  // forward state that is cheap to rebuild: warp, block statistics
   HIPC(launch_warp(P, tar, tarw, stream), "warp");
   HIPC(launch_block_stats(P, ref, STEREO_F32, P.p.pitch_ref, m.zX, m.isdX, stream), "stats");
   HIPC(launch_block_stats(P, tarw, STEREO_F32, W, m.zY, m.isdY, stream), "stats");
-  LAUNCH("weight sums", weight_sum_kernel<float>, rows, dim3(256), 0, stream, ref,
-         P.p.pitch_ref, W, H, P.R, c.ks2, c.kr2, Wp);
 
-  const float invT = 1.0f / P.p.softargmin_T;
   const int n = (2 * r + 1) * (2 * r + 1);
   for (int d0 = 0; d0 < D; d0 += DT) {
     const int nl = std::min(DT, D - d0);
-    // recompute this tile of the cost volume and of the aggregated volume
+    // recompute this tile of the cost volume
     HIPC(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, Ct, W, W, HW, 0, stream, d0,
                     d0 + nl), "ncc tile");
+    // pass 1: aggregated costs E, the softmax adjoint dE, dE / W_p, aP, A1 (and W_p)
     BilArgs a{};
     a.C = Ct; a.c_slice = HW; a.c_pitch = W;
     a.guide = ref; a.guide_dt = STEREO_F32; a.guide_pitch = P.p.pitch_ref;
     a.levels = nl;
-    a.E = Et;
-    HIPC(launch_bilateral(P, a, 0, stream), "aggregation tile");
-    LAUNCH("soft-argmin adjoint", soft_grad_e_kernel, flat, dim3(256), 0, stream, Et, sm_m,
-           sm_logZ, sm_dh, grad_disp, Wp, W, H, d0, nl, invT, (float)(1.0 - plane[1]), gEt, Gt,
-           aP);
-    // dC(q, d) = sum_p w(q, p) dE(p, d) / W_p  (weights are symmetric)
+    a.E = Gt;
+    a.sm_m = const_cast<float*>(sm_m);
+    a.sm_logZ = const_cast<float*>(sm_logZ);
+    a.sm_dh = const_cast<float*>(sm_dh);
+    a.gD = grad_disp;
+    a.aP = aP; a.A1 = A1; a.A2 = A2;
+    a.Wp = d0 == 0 ? Wp : nullptr;
+    a.d_first = d0;
+    a.plane[0] = plane[0]; a.plane[1] = plane[1]; a.plane[2] = plane[2];
+    HIPC(launch_bilateral(P, a, 5, stream), "aggregation + softmax adjoint");
+    // pass 2: dC(q, d) = sum_p w(q, p) dE(p, d) / W_p (weights are symmetric), A2
     a.C = Gt;
     a.E = gCt;
-    HIPC(launch_bilateral(P, a, 4, stream), "aggregation adjoint");
-    st = guide_grad(P, Ct, gEt, ref, Wp, nl, c.ks2, c.kr2, A1, A2, stream);
-    if (st != STEREO_OK) return st;
+    a.cpix = Ct;
+    HIPC(launch_bilateral(P, a, 6, stream), "aggregation adjoint");
     LAUNCH("ncc adjoint coefficients", ncc_coef_kernel, rows, dim3(256), 0, stream, Ct, gCt,
            m.zX, m.isdX, m.zY, m.isdY, W, H, r, d0, nl, 1.0f / (float)n, Fa, FamX, Fg, FgmY,
            Sb, SbmX, SamY);
