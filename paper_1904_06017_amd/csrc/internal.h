@@ -49,9 +49,11 @@ enum GradRegion {
   GR_WP, GR_AP, GR_A1, GR_A2,
   GR_SUMS,                                      // [3][H][W]: alpha muY, beta, beta muX
   GR_GX, GR_GTARW,
-  GR_CT, GR_GT, GR_GCT, GR_FA,                 // GR_FA: [4][DT][H][W] alpha maps
-  GR_BA,                                        // [4][DT][HV][WVX] boxes
-  GR_BS,                                        // [3][HV][WVX] boxes of the sums
+  GR_CT, GR_GT, GR_GCT, GR_FA,                 // GR_FA: [DT][H][W] alpha maps
+  GR_BA,                                        // [DT][HV][WVX] boxes of alpha
+  GR_BS,                                        // [3][HV][WVX] boxes of the X sums
+  GR_SY,                                        // [3][H][W+D-1] target-side sums
+  GR_BSY,                                       // [3][HV][WVY] their boxes
   GR_GXV, GR_GYV, GR_GTARFIX, GR_PART_A, GR_PART_B, GR_SCRATCH, GR_COUNT
 };
 

@@ -74,14 +74,14 @@ guide_finish_kernel(const GT* __restrict__ g, int64_t gpitch, const float* __res
 // the gradient of the reference block element i is
 //   alpha (Y_i - muY) - beta (X_i - muX),
 // and of the target block element  alpha (X_i - muX) - gamma (Y_i - muY).
-// Per level maps: alpha, alpha muX, gamma, gamma muY; per pixel sums over
-// levels (all tiles): beta, beta muX, alpha muY.
+// Per level map: alpha; per reference pixel sums over levels (all tiles):
+// beta, beta muX, alpha muY.  The target-side level sums are gathered along
+// the shear by ncc_shear_kernel.
 __global__ void __launch_bounds__(kT)
 ncc_coef_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
                 const float* __restrict__ zX, const float* __restrict__ isdX,
                 const float* __restrict__ zY, const float* __restrict__ isdY, int W, int H,
                 int r, int d_first, int nlev, float inv_n, float* __restrict__ Fa,
-                float* __restrict__ FamX, float* __restrict__ Fg, float* __restrict__ FgmY,
                 float* __restrict__ Sb, float* __restrict__ SbmX, float* __restrict__ SamY) {
   const int x = blockIdx.x * kT + threadIdx.x, y = blockIdx.y;
   if (x >= W) return;
@@ -102,11 +102,7 @@ ncc_coef_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
     const float rho = 1.0f - Ct[t * HW + p];
     const float al = A * iX * iY;
     const float be = A * rho * iX * iX;
-    const float ga = A * rho * iY * iY;
     Fa[t * HW + p] = al;
-    FamX[t * HW + p] = al * mX;
-    Fg[t * HW + p] = ga;
-    FgmY[t * HW + p] = ga * mY;
     sb += be;
     sbm = fmaf(be, mX, sbm);
     sam = fmaf(al, mY, sam);
@@ -116,42 +112,91 @@ ncc_coef_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
   SamY[p] = sam;
 }
 
-// Box sums onto the virtual X domain: B(j) = sum_{o in [-r,r]^2} F(j - o) over
-// image pixels j - o.  One lane per virtual column, walking down the rows with
-// a ring of 2r+1 horizontal sums (fixed order: horizontal j = -r..r, then
-// vertical i = -r..r).  grid.z indexes the maps (level-major).
+// Target-side level sums along the shear, for one level tile.  The target
+// block of pixel x at level d is centred at column m = x - d, so the sums over
+// levels of the three target terms are maps over m in [-(D-1), W):
+//   SaX(m) += sum_d alpha(m+d, d) muX(m+d),  Sg(m) += sum_d gamma(m+d, d),
+//   SgY(m) += sum_d gamma(m+d, d) muY(m).
+// Maps are [H][W + D - 1], column index m + D - 1.
+__global__ void __launch_bounds__(kT)
+ncc_shear_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
+                 const float* __restrict__ zX, const float* __restrict__ isdX,
+                 const float* __restrict__ zY, const float* __restrict__ isdY, int W, int H,
+                 int D, int r, int d_first, int nlev, float inv_n, float* __restrict__ SaX,
+                 float* __restrict__ Sg, float* __restrict__ SgY) {
+  const int WY = W + D - 1;
+  const int mi = blockIdx.x * kT + threadIdx.x, y = blockIdx.y;
+  if (mi >= WY) return;
+  const int m = mi - (D - 1);
+  const int64_t HW = (int64_t)W * H;
+  const int SW = W + 2 * r;
+  const int64_t ro = (int64_t)y * SW;
+  const int cy = max(m, -r) + r;
+  const float iY = isdY[ro + cy];
+  const float mY = iY != 0.0f ? zY[ro + cy] / iY : 0.0f;
+  const int64_t q = (int64_t)y * WY + mi;
+  float sax = SaX[q], sg = Sg[q];
+  for (int t = 0; t < nlev; ++t) {
+    const int x = m + d_first + t;
+    if (x < 0 || x >= W) continue;
+    const float iX = isdX[ro + x + r];
+    const float mX = iX != 0.0f ? zX[ro + x + r] / iX : 0.0f;
+    const int64_t p = (int64_t)y * W + x;
+    const bool flat = (iX == 0.0f) || (iY == 0.0f);
+    const float A = flat ? 0.0f : -gCt[t * HW + p] * inv_n;
+    const float rho = 1.0f - Ct[t * HW + p];
+    sax = fmaf(A * iX * iY, mX, sax);
+    sg = fmaf(A * rho, iY * iY, sg);
+  }
+  SaX[q] = sax;
+  Sg[q] = sg;
+  SgY[q] = sg * mY;
+}
+
+// Box sums onto a virtual domain: B(j) = sum_{o in [-r,r]^2} F(j - o) over
+// image pixels j - o (F is [H][W], B is [H + 2r][W + 2r], virtual position j
+// at index j + r).  A workgroup (one wave) covers BX_TX virtual columns x
+// BX_TY virtual rows of one map: the (BX_TY + 2r) x (BX_TX + 2r) input tile,
+// zero outside the image, is staged in LDS; each lane walks down its column
+// with a ring of 2r+1 horizontal sums (fixed order: horizontal j = -r..r,
+// then vertical i = -r..r).  grid.z indexes the maps.
 constexpr int BX_TX = 64, BX_TY = 32;
 
 template <int r>
 __global__ void __launch_bounds__(64)
 box_kernel(const float* __restrict__ F, int W, int H, float* __restrict__ B) {
   constexpr int K = 2 * r + 1;
+  constexpr int TWI = BX_TX + 2 * r, THI = BX_TY + 2 * r;
+  __shared__ float tile[THI * TWI];
   const int WV = W + 2 * r, HV = H + 2 * r;
   const int64_t HW = (int64_t)W * H;
   const float* f = F + blockIdx.z * HW;
   float* b = B + (int64_t)blockIdx.z * HV * WV;
-  const int jx = (int)(blockIdx.x * BX_TX + threadIdx.x) - r;     // virtual column
-  const int jy0 = (int)(blockIdx.y * BX_TY) - r;                  // first virtual row
+  const int vx0 = blockIdx.x * BX_TX - r;          // first virtual column (image coords)
+  const int vy0 = blockIdx.y * BX_TY - r;          // first virtual row (image coords)
+  const int ix0 = vx0 - r, iy0 = vy0 - r;          // first input column / row
+  for (int i = threadIdx.x; i < THI * TWI; i += 64) {
+    const int yy = i / TWI, xx = i - yy * TWI;
+    const int iy = iy0 + yy, ix = ix0 + xx;
+    tile[i] = (iy >= 0 && iy < H && ix >= 0 && ix < W) ? f[(int64_t)iy * W + ix] : 0.0f;
+  }
+  __syncthreads();
+  const int c = threadIdx.x;
+  const int jx = vx0 + c;                          // this lane's virtual column
   float ring[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) ring[i] = 0.0f;
-  const int rows = BX_TY + 2 * r;
-  for (int yb = 0; yb < rows; yb += K) {
+  for (int yb = 0; yb < THI; yb += K) {
 #pragma unroll
     for (int s = 0; s < K; ++s) {
       const int yy = yb + s;
-      if (yy >= rows) break;
-      const int iy = jy0 - r + yy;                  // input row (image coords)
-      float h = 0.0f;
-      if (iy >= 0 && iy < H) {
+      if (yy >= THI) break;
+      const float* trow = tile + yy * TWI + c;
+      float h = trow[0];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const int ix = jx + r - j;                // j - o with o_x = j - r ... (-r..r)
-          h += (ix >= 0 && ix < W) ? f[(int64_t)iy * W + ix] : 0.0f;
-        }
-      }
+      for (int j = 1; j < K; ++j) h += trow[j];
       ring[s] = h;
-      const int oy = jy0 + yy - 2 * r;              // virtual row completed
+      const int oy = vy0 + yy - 2 * r;             // virtual row completed (image coords)
       if (yy >= 2 * r && oy < H + r && jx < W + r) {
         float S = ring[(s + 1) % K];
 #pragma unroll
@@ -180,20 +225,17 @@ assemble_x_kernel(const float* __restrict__ Ba, const float* __restrict__ tarw, 
   gXv[jv] += acc;
 }
 
-// gYv(k) += sum_{d in tile} [Xv(k+d) B_a(k+d) - B_amX(k+d) - Yv(k) B_g(k+d) + B_gmY(k+d)]
-// on the virtual Y domain; B at virtual X column k + d (zero outside it).
+// gYv(k) += sum_{d in tile} Xv(k+d) B_alpha,d(k+d) on the virtual Y domain;
+// B at virtual X column k + d (zero outside it).
 template <typename T>
 __global__ void __launch_bounds__(kT)
-assemble_y_kernel(const float* __restrict__ Ba, const float* __restrict__ BamX,
-                  const float* __restrict__ Bg, const float* __restrict__ BgmY,
-                  const T* __restrict__ ref, int64_t rpitch, const float* __restrict__ tarw,
+assemble_y_kernel(const float* __restrict__ Ba, const T* __restrict__ ref, int64_t rpitch,
                   int W, int H, int D, int r, int d_first, int nlev, float* __restrict__ gYv) {
   const int WVX = W + 2 * r, HV = H + 2 * r, WVY = W + D - 1 + 2 * r;
   const int ky = blockIdx.x * kT + threadIdx.x, vy = blockIdx.y;   // ky: Y-domain column index
   if (ky >= WVY) return;
   const int kx = ky - (D - 1) - r;                                  // image column of k
   const int y = clampi(vy - r, 0, H - 1);
-  const float yv = tarw[(int64_t)y * W + clampi(kx, 0, W - 1)] - kOffset;
   const int64_t HVWV = (int64_t)HV * WVX;
   float acc = 0.0f;
   for (int t = 0; t < nlev; ++t) {
@@ -201,9 +243,24 @@ assemble_y_kernel(const float* __restrict__ Ba, const float* __restrict__ BamX,
     if (jx < -r || jx >= W + r) continue;
     const int64_t j = (int64_t)t * HVWV + (int64_t)vy * WVX + (jx + r);
     const float xv = ldf(ref + (int64_t)y * rpitch + clampi(jx, 0, W - 1)) - kOffset;
-    acc += fmaf(xv, Ba[j], -BamX[j]) + fmaf(-yv, Bg[j], BgmY[j]);
+    acc = fmaf(xv, Ba[j], acc);
   }
   gYv[(int64_t)vy * WVY + ky] += acc;
+}
+
+// Target side terms summed over all levels (virtual Y domain):
+//   gYv(k) += -B(SaX)(k) - Yv(k) B(Sg)(k) + B(SgY)(k)
+__global__ void __launch_bounds__(kT)
+y_complete_kernel(const float* __restrict__ BSaX, const float* __restrict__ BSg,
+                  const float* __restrict__ BSgY, const float* __restrict__ tarw, int W, int H,
+                  int D, int r, float* __restrict__ gYv) {
+  const int WVY = W + D - 1 + 2 * r;
+  const int ky = blockIdx.x * kT + threadIdx.x, vy = blockIdx.y;
+  if (ky >= WVY) return;
+  const int64_t k = (int64_t)vy * WVY + ky;
+  const int kx = ky - (D - 1) - r;
+  const float yv = tarw[(int64_t)clampi(vy - r, 0, H - 1) * W + clampi(kx, 0, W - 1)] - kOffset;
+  gYv[k] += -BSaX[k] - yv * BSg[k] + BSgY[k];
 }
 
 // X side terms summed over all levels:
@@ -417,9 +474,11 @@ size_t grad_layout(Plan& P, size_t o) {
   for (int i = GR_WP; i <= GR_GTARW; ++i) sz[i] = f4 * HW;
   sz[GR_SUMS] = 3 * f4 * HW;
   for (int i = GR_CT; i <= GR_GCT; ++i) sz[i] = f4 * DT * HW;
-  sz[GR_FA] = 4 * f4 * DT * HW;
-  sz[GR_BA] = 4 * f4 * DT * HV * WVX;
+  sz[GR_FA] = f4 * DT * HW;
+  sz[GR_BA] = f4 * DT * HV * WVX;
   sz[GR_BS] = 3 * f4 * HV * WVX;
+  sz[GR_SY] = 3 * f4 * (size_t)P.H * (P.W + P.D - 1);
+  sz[GR_BSY] = 3 * f4 * HV * WVY;
   sz[GR_GXV] = f4 * HV * WVX;
   sz[GR_GYV] = f4 * HV * WVY;
   sz[GR_GTARFIX] = sizeof(unsigned long long) * HW;
@@ -488,15 +547,17 @@ stereo_status zero_f(float* p, int64_t n, hipStream_t s) {
 }
 
 template <int r>
-stereo_status box_r(const Plan& P, const float* F, int nmaps, float* B, hipStream_t s) {
-  dim3 grid((P.W + 2 * r + 63) / 64, (P.H + 2 * r + 31) / 32, nmaps);
-  LAUNCH("box sums", (box_kernel<r>), grid, dim3(64), 0, s, F, P.W, P.H, B);
+stereo_status box_r(int W, int H, const float* F, int nmaps, float* B, hipStream_t s) {
+  dim3 grid((W + 2 * r + BX_TX - 1) / BX_TX, (H + 2 * r + BX_TY - 1) / BX_TY, nmaps);
+  LAUNCH("box sums", (box_kernel<r>), grid, dim3(64), 0, s, F, W, H, B);
   return STEREO_OK;
 }
 
-stereo_status box(const Plan& P, const float* F, int nmaps, float* B, hipStream_t s) {
+// Box sums of nmaps [H][width] maps onto [H + 2r][width + 2r].
+stereo_status box(const Plan& P, int width, const float* F, int nmaps, float* B,
+                  hipStream_t s) {
   switch (P.r) {
-#define BOX_CASE(R_) case R_: return box_r<R_>(P, F, nmaps, B, s);
+#define BOX_CASE(R_) case R_: return box_r<R_>(width, P.H, F, nmaps, B, s);
     BOX_CASE(1) BOX_CASE(2) BOX_CASE(3) BOX_CASE(4) BOX_CASE(5) BOX_CASE(6) BOX_CASE(7) BOX_CASE(8)
 #undef BOX_CASE
     default: return fail(STEREO_ERR_UNSUPPORTED, "ncc_radius");
@@ -569,10 +630,12 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
   float *gX = R_(GR_GX), *gtarw = R_(GR_GTARW);
   float *Ct = R_(GR_CT), *Gt = R_(GR_GT), *gCt = R_(GR_GCT);
   float* Fa = R_(GR_FA);
-  float *FamX = Fa + DT * HW, *Fg = Fa + 2 * DT * HW, *FgmY = Fa + 3 * DT * HW;
   float* Ba = R_(GR_BA);
-  float *BamX = Ba + DT * HVWV, *Bg = Ba + 2 * DT * HVWV, *BgmY = Ba + 3 * DT * HVWV;
   float* BS = R_(GR_BS);
+  const int WY = W + D - 1;
+  const int64_t HWY = (int64_t)H * WY, HVWVY = (int64_t)HV * WVY;
+  float *SaX = R_(GR_SY), *Sg = SaX + HWY, *SgY = SaX + 2 * HWY;
+  float* BSY = R_(GR_BSY);
   float *gXv = R_(GR_GXV), *gYv = R_(GR_GYV);
   auto* gfix = at<unsigned long long>(ws, P.g_off[GR_GTARFIX]);
   double* partA = at<double>(ws, P.g_off[GR_PART_A]);
@@ -589,6 +652,7 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
     st = zero_f(z, HW, stream);
     if (st != STEREO_OK) return st;
   }
+  if ((st = zero_f(SaX, 2 * HWY, stream)) != STEREO_OK) return st;
   if ((st = zero_f(gXv, HVWV, stream)) != STEREO_OK) return st;
   if ((st = zero_f(gYv, (int64_t)HV * WVY, stream)) != STEREO_OK) return st;
   LAUNCH("zero", zero_u64_kernel, flat, dim3(256), 0, stream, gfix, HW);
@@ -625,18 +689,22 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
     a.cpix = Ct;
     HIPC(launch_bilateral(P, a, 6, stream), "aggregation adjoint");
     LAUNCH("ncc adjoint coefficients", ncc_coef_kernel, rows, dim3(256), 0, stream, Ct, gCt,
-           m.zX, m.isdX, m.zY, m.isdY, W, H, r, d0, nl, 1.0f / (float)n, Fa, FamX, Fg, FgmY,
-           Sb, SbmX, SamY);
-    if ((st = box(P, Fa, 4 * DT, Ba, stream)) != STEREO_OK) return st;
+           m.zX, m.isdX, m.zY, m.isdY, W, H, r, d0, nl, 1.0f / (float)n, Fa, Sb, SbmX, SamY);
+    LAUNCH("ncc adjoint shear sums", ncc_shear_kernel, dim3((WY + 255) / 256, H), dim3(256), 0,
+           stream, Ct, gCt, m.zX, m.isdX, m.zY, m.isdY, W, H, D, r, d0, nl, 1.0f / (float)n,
+           SaX, Sg, SgY);
+    if ((st = box(P, W, Fa, nl, Ba, stream)) != STEREO_OK) return st;
     LAUNCH("ncc adjoint (reference side)", assemble_x_kernel, dim3((WVX + 255) / 256, HV),
            dim3(256), 0, stream, Ba, tarw, W, H, r, d0, nl, gXv);
     LAUNCH("ncc adjoint (target side)", assemble_y_kernel<float>, dim3((WVY + 255) / 256, HV),
-           dim3(256), 0, stream, Ba, BamX, Bg, BgmY, ref, P.p.pitch_ref, tarw, W, H, D, r, d0,
-           nl, gYv);
+           dim3(256), 0, stream, Ba, ref, P.p.pitch_ref, W, H, D, r, d0, nl, gYv);
   }
-  if ((st = box(P, SamY, 3, BS, stream)) != STEREO_OK) return st;
+  if ((st = box(P, W, SamY, 3, BS, stream)) != STEREO_OK) return st;
   LAUNCH("ncc adjoint (level sums)", x_complete_kernel<float>, dim3((WVX + 255) / 256, HV),
          dim3(256), 0, stream, BS, BS + HVWV, BS + 2 * HVWV, ref, P.p.pitch_ref, W, H, r, gXv);
+  if ((st = box(P, WY, SaX, 3, BSY, stream)) != STEREO_OK) return st;
+  LAUNCH("ncc adjoint (target level sums)", y_complete_kernel, dim3((WVY + 255) / 256, HV),
+         dim3(256), 0, stream, BSY, BSY + HVWVY, BSY + 2 * HVWVY, tarw, W, H, D, r, gYv);
   LAUNCH("fold", fold_kernel, rows, dim3(256), 0, stream, gXv, W, H, r, r, gX);
   LAUNCH("fold", fold_kernel, rows, dim3(256), 0, stream, gYv, W, H, r, D - 1 + r, gtarw);
   LAUNCH("guide gradient", guide_finish_kernel<float>, rows, dim3(256), 0, stream, ref,
