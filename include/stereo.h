@@ -112,6 +112,9 @@ stereo_status stereo_plan_get_params(stereo_plan_t plan, stereo_params* out);
  *   "agg_levels_u8", "agg_levels_f32": disparity levels staged per pass of
  *   the aggregation kernel for 8-bit / float guides, 8 or 16 (default 8);
  *   results are bitwise identical for every value;
+ *   "ncc_levels": disparity levels per workgroup of the NCC cost kernel, 16,
+ *   32 or 64, or 0 (default: 64, 32 or 16, the largest block the launch's
+ *   levels fill); results are bitwise identical for every value;
  *   "grad_levels": levels recomputed per tile by stereo_backward, a multiple
  *   of 4 in 4..64 (default 16); changes the workspace size and the FP32
  *   summation order of the gradients (not their value beyond rounding).

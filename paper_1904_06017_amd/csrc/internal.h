@@ -37,6 +37,8 @@ struct Plan {
   // tuning (stereo_plan_set_tuning): levels per aggregation pass by guide type
   int agg_levels_u8 = 8;
   int agg_levels_f32 = 8;
+  int ncc_levels = 0;   // levels per NCC workgroup (16, 32 or 64; DC / 4 waves);
+                        // 0: 64 / 32 / 16 by the levels of the launch
   // differentiable form (F32 plans): levels recomputed per backward tile and
   // the workspace regions it uses (offsets from the workspace base)
   int grad_levels = 16;

@@ -4,6 +4,8 @@
 // Layout: images row-major with an element pitch; statistics maps [H][W+2r]
 // over block centres x in [-r, W + r) (block reads are clamped, so centres
 // further out repeat the edge values); cost slices [D][H][pitch].
+#include <type_traits>
+
 #include "internal.h"
 
 namespace stereo {
@@ -122,13 +124,14 @@ block_stats_kernel(const T* __restrict__ img, int64_t pitch, int W, int H, int r
 // The unshifted operand A (X' for anchor 0, Y' for anchor 1) and the
 // level-shifted operand B are staged in LDS with clamped reads.
 constexpr int NC_TX = 64, NC_TY = 32, NC_DC = 16, NC_DW = 4;
+// NC_DC is the default level block; a workgroup of DC levels has DC / 4 waves.
 
-template <int r>
+template <int r, int DC = NC_DC>
 struct NccGeom {
   static constexpr int K = 2 * r + 1;
   static constexpr int ROWS = NC_TY + 2 * r;
   static constexpr int AW = NC_TX + 2 * r;
-  static constexpr int BW = NC_TX + 2 * r + NC_DC - 1;
+  static constexpr int BW = NC_TX + 2 * r + DC - 1;
   static constexpr size_t lds_bytes = sizeof(float) * (size_t)ROWS * (AW + BW);
 };
 
@@ -136,7 +139,7 @@ struct NccGeom {
 // float4 (out_slice and out_pitch in float4 units; levels at or past d_end
 // inside the last quad are written as 0), QUAD = 0 the planar layout
 // [levels][H][pitch].
-template <int r, typename T, int QUAD>
+template <int r, typename T, int QUAD, int DC>
 __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_pitch,
                                          const float* __restrict__ tarw, int W, int H,
                                          int d_first, int d_end,
@@ -147,19 +150,19 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
                                          float* __restrict__ C, int out_w, int64_t out_pitch,
                                          int64_t out_slice, int anchor, float* sm, int bx,
                                          int by, int bz) {
-  using G = NccGeom<r>;
+  using G = NccGeom<r, DC>;
   constexpr int K = G::K;
   float* As = sm;                         // [ROWS][AW]
   float* Bs = sm + G::ROWS * G::AW;       // [ROWS][BW]
   const int x0 = bx * NC_TX;
   const int y0 = by * NC_TY;
-  const int d0 = d_first + bz * NC_DC;
+  const int d0 = d_first + bz * DC;
   const int SW = W + 2 * r;
   // image column of A[.][0] and B[.][0]
   //   anchor 0: A = X' at x + j - r, B = Y' at x - d + j - r
   //   anchor 1: A = Y' at x + j - r, B = X' at x + d + j - r
   const int axo = x0 - r;
-  const int bxo = anchor ? x0 - r + d0 : x0 - r - d0 - (NC_DC - 1);
+  const int bxo = anchor ? x0 - r + d0 : x0 - r - d0 - (DC - 1);
   for (int i = threadIdx.x; i < G::ROWS * G::BW; i += blockDim.x) {
     const int yy = i / G::BW, xx = i - yy * G::BW;
     const int gy = min(max(y0 - r + yy, 0), H - 1);
@@ -181,7 +184,7 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
 #pragma unroll
   for (int k = 0; k < NC_DW; ++k) {
     const int dc = wave * NC_DW + k;
-    boff[k] = anchor ? dc : (NC_DC - 1 - dc);
+    boff[k] = anchor ? dc : (DC - 1 - dc);
   }
   const float inv_n = 1.0f / (float)(K * K);
   float ring[NC_DW][K];
@@ -241,8 +244,8 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
   }
 }
 
-template <int r, typename T, int QUAD>
-__global__ void __launch_bounds__(256)
+template <int r, typename T, int QUAD, int DC>
+__global__ void __launch_bounds__(16 * DC)
 ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
            const float* __restrict__ tarw, int W, int H, int d_first, int d_end,
            const float* __restrict__ zX, const float* __restrict__ isdX,
@@ -250,7 +253,7 @@ ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
            float* __restrict__ C, int out_w, int64_t out_pitch,
            int64_t out_slice, int anchor) {
   extern __shared__ float sm[];
-  ncc_body<r, T, QUAD>(ref, ref_pitch, tarw, W, H, d_first, d_end, zX, isdX, zY, isdY, C,
+  ncc_body<r, T, QUAD, DC>(ref, ref_pitch, tarw, W, H, d_first, d_end, zX, isdX, zY, isdY, C,
                        out_w, out_pitch, out_slice, anchor, sm, blockIdx.x, blockIdx.y,
                        blockIdx.z);
 }
@@ -296,9 +299,29 @@ ncc_jobs_kernel(const NccJob* __restrict__ jobs, const int* __restrict__ first, 
   const int l = blockIdx.x - first[j];
   const int gxy = J.gx * J.gy;
   const int bz = l / gxy, rem = l - bz * gxy;
-  ncc_body<r, T, QUAD>(static_cast<const T*>(J.ref), J.ref_pitch, J.tarw, J.W, J.H, J.d_first,
+  ncc_body<r, T, QUAD, NC_DC>(static_cast<const T*>(J.ref), J.ref_pitch, J.tarw, J.W, J.H, J.d_first,
                        J.d_end, J.zX, J.isdX, J.zY, J.isdY, J.C, J.out_w, J.out_pitch,
                        J.out_slice, J.anchor, sm, rem % J.gx, rem / J.gx, bz);
+}
+
+template <int r, typename T, int DC>
+hipError_t launch_ncc_rdc(const Plan& P, const T* ref, const float* tar_w, const float* zX,
+                          const float* isdX, const float* zY, const float* isdY, float* C,
+                          int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
+                          int d_first, int d_end, int quad, hipStream_t s) {
+  dim3 grid((out_w + NC_TX - 1) / NC_TX, (P.H + NC_TY - 1) / NC_TY,
+            (d_end - d_first + DC - 1) / DC);
+  if (quad)
+    hipLaunchKernelGGL((ncc_kernel<r, T, 1, DC>), grid, dim3(16 * DC),
+                       (NccGeom<r, DC>::lds_bytes), s, ref, P.p.pitch_ref, tar_w, P.W, P.H,
+                       d_first, d_end, zX, isdX, zY, isdY, C, out_w, out_pitch, out_slice,
+                       anchor);
+  else
+    hipLaunchKernelGGL((ncc_kernel<r, T, 0, DC>), grid, dim3(16 * DC),
+                       (NccGeom<r, DC>::lds_bytes), s, ref, P.p.pitch_ref, tar_w, P.W, P.H,
+                       d_first, d_end, zX, isdX, zY, isdY, C, out_w, out_pitch, out_slice,
+                       anchor);
+  return hipGetLastError();
 }
 
 template <int r, typename T>
@@ -306,17 +329,22 @@ hipError_t launch_ncc_r(const Plan& P, const T* ref, const float* tar_w, const f
                         const float* isdX, const float* zY, const float* isdY, float* C,
                         int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
                         int d_first, int d_end, int quad, hipStream_t s) {
-  dim3 grid((out_w + NC_TX - 1) / NC_TX, (P.H + NC_TY - 1) / NC_TY,
-            (d_end - d_first + NC_DC - 1) / NC_DC);
-  if (quad)
-    hipLaunchKernelGGL((ncc_kernel<r, T, 1>), grid, dim3(256), NccGeom<r>::lds_bytes, s, ref,
-                       P.p.pitch_ref, tar_w, P.W, P.H, d_first, d_end, zX, isdX, zY, isdY, C,
-                       out_w, out_pitch, out_slice, anchor);
-  else
-    hipLaunchKernelGGL((ncc_kernel<r, T, 0>), grid, dim3(256), NccGeom<r>::lds_bytes, s, ref,
-                       P.p.pitch_ref, tar_w, P.W, P.H, d_first, d_end, zX, isdX, zY, isdY, C,
-                       out_w, out_pitch, out_slice, anchor);
-  return hipGetLastError();
+  int dc = P.ncc_levels;
+  if (dc == 0) {                        // automatic: the largest block the levels fill
+    const int nl = d_end - d_first;
+    dc = nl >= 64 ? 64 : nl >= 32 ? 32 : 16;
+  }
+  switch (dc) {
+    case 32:
+      return launch_ncc_rdc<r, T, 32>(P, ref, tar_w, zX, isdX, zY, isdY, C, out_w, out_pitch,
+                                      out_slice, anchor, d_first, d_end, quad, s);
+    case 64:
+      return launch_ncc_rdc<r, T, 64>(P, ref, tar_w, zX, isdX, zY, isdY, C, out_w, out_pitch,
+                                      out_slice, anchor, d_first, d_end, quad, s);
+    default:
+      return launch_ncc_rdc<r, T, 16>(P, ref, tar_w, zX, isdX, zY, isdY, C, out_w, out_pitch,
+                                      out_slice, anchor, d_first, d_end, quad, s);
+  }
 }
 
 template <typename T>
@@ -403,10 +431,10 @@ template <int r, typename T>
 hipError_t ncc_jobs_r(int quad, const NccJob* jobs, const int* first, int n, int blocks,
                       hipStream_t s) {
   if (quad)
-    hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 1>), dim3(blocks), dim3(256),
+    hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 1>), dim3(blocks), dim3(16 * NC_DC),
                        NccGeom<r>::lds_bytes, s, jobs, first, n);
   else
-    hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 0>), dim3(blocks), dim3(256),
+    hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 0>), dim3(blocks), dim3(16 * NC_DC),
                        NccGeom<r>::lds_bytes, s, jobs, first, n);
   return hipGetLastError();
 }

@@ -117,6 +117,10 @@ def test_tuning_keys(lib):
     assert lib.stereo_plan_set_tuning(h, b"agg_levels_f32", 16) == 0
     assert lib.stereo_plan_get_tuning(h, b"agg_levels_f32", ctypes.byref(v)) == 0 and v.value == 16
     assert lib.stereo_plan_set_tuning(h, b"agg_levels_f32", 12) == 1
+    assert lib.stereo_plan_get_tuning(h, b"ncc_levels", ctypes.byref(v)) == 0 and v.value == 0
+    assert lib.stereo_plan_set_tuning(h, b"ncc_levels", 64) == 0
+    assert lib.stereo_plan_get_tuning(h, b"ncc_levels", ctypes.byref(v)) == 0 and v.value == 64
+    assert lib.stereo_plan_set_tuning(h, b"ncc_levels", 48) == 1
     assert lib.stereo_plan_set_tuning(h, b"no_such_key", 8) == 1
     lib.stereo_plan_destroy(h)
 

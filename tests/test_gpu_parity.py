@@ -156,14 +156,16 @@ def test_tuning_variants_are_bitwise_identical(name):
     w, sc, ora = case(name)
     ref, tar = _dev(sc.ref), _dev(sc.tar)
     outs = []
-    for lv in (8, 16):
+    for lv, nl in ((8, 16), (16, 32), (8, 64)):
         plan = api.Plan.from_workload(w)
         plan.set_tuning("agg_levels_u8", lv)
         plan.set_tuning("agg_levels_f32", lv)
+        plan.set_tuning("ncc_levels", nl)
         o = api.match(plan, ref, tar, want_target=True)
         outs.append({k: _host(v) for k, v in o.items()})
-    for k in outs[0]:
-        assert np.array_equal(outs[0][k], outs[1][k], equal_nan=True), k
+    for o in outs[1:]:
+        for k in outs[0]:
+            assert np.array_equal(outs[0][k], o[k], equal_nan=True), k
 
 
 def test_near_ties_are_rare():
