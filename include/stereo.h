@@ -206,6 +206,17 @@ stereo_status stereo_road_transform(stereo_plan_t plan, const float* disp,
                                     void* ws, size_t ws_bytes,
                                     hipStream_t stream);
 
+/* ---- road damage on the transformed map, Sec. 4.4.3 -----------------------
+ * After Eq. (29) the road surface is flat at delta_t and damage (potholes,
+ * cracks: farther away, smaller disparity) lies below it.  Writes
+ * mask[p] = 1 where disp_t[p] is finite and disp_t[p] < delta_t - tau, else 0
+ * (the comparison in FP32, with delta_t - tau rounded to FP32 once).
+ * disp_t: [H][W] FP32 as written by stereo_road_transform; mask: [H][W]
+ * uint8, caller-owned.  tau > 0 is the depth threshold in pixels of
+ * disparity.  No workspace, no host synchronisation. */
+stereo_status stereo_damage_mask(stereo_plan_t plan, const float* disp_t, float delta_t,
+                                 float tau, uint8_t* mask, hipStream_t stream);
+
 /* ---- batched form ----------------------------------------------------------
  * Many pairs of uneven size and disparity range (each with its own plan) in
  * one workspace and one captured graph.  Per pair, results are bitwise those

@@ -25,6 +25,17 @@ def mde_per_s(u_max, v_max, d_max, t_seconds):
     return u_max * v_max * d_max / t_seconds * 1e-6
 
 
+def iou(pred, truth, sel=None):
+    """Intersection over union of two boolean masks (optionally restricted to
+    sel); 1.0 when both are empty."""
+    a = np.asarray(pred, bool)
+    b = np.asarray(truth, bool)
+    if sel is not None:
+        a, b = a[sel], b[sel]
+    union = np.count_nonzero(a | b)
+    return 1.0 if union == 0 else float(np.count_nonzero(a & b) / union)
+
+
 def sigma_d(values):
     """Eq. (37): population standard deviation of transformed disparities."""
     s = np.asarray(values, np.float64).ravel()

@@ -164,6 +164,19 @@ def transform(disp, fit: RoadFit, delta_t=0.0):
             + delta_t)
 
 
+def damage_mask(disp_t, delta_t=0.0, tau=0.5):
+    """Damage on the transformed map (Sec. 4.4.3): after Eq. (29) the road is
+    flat at delta_t and potholes / cracks (farther away, smaller disparity)
+    lie below it.  A pixel is damage when its finite transformed disparity is
+    more than tau below delta_t.  The comparison is taken in FP32 (a float
+    decides a boolean; the kernel's precision), with delta_t - tau rounded to
+    FP32 once."""
+    d = np.asarray(disp_t, np.float32)
+    level = np.float32(np.float32(delta_t) - np.float32(tau))
+    with np.errstate(invalid="ignore"):
+        return np.isfinite(d) & (d < level)
+
+
 def road_transform(disp, valid=None, mask=None, psi0=0.0, lambda0=LAMBDA0,
                    delta_psi=DELTA_PSI, max_iter=100, delta_t=0.0):
     H, W = np.shape(disp)

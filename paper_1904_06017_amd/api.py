@@ -234,6 +234,17 @@ def road_transform(plan: Plan, disp, mask=None, psi_init=0.0, lambda0=LAMBDA0,
     return (road_fit_from_bytes(fit_buf) if read_fit else fit_buf), out
 
 
+def damage_mask(plan: Plan, disp_t, delta_t=0.0, tau=0.5, out=None):
+    """uint8 [H][W]: 1 where the transformed disparity lies more than tau
+    below the flattened road level delta_t (Sec. 4.4.3)."""
+    _need(disp_t, torch.float32, (plan.H, plan.W), "disp_t")
+    if out is None:
+        out = torch.empty((plan.H, plan.W), dtype=torch.uint8, device=disp_t.device)
+    check(_lib.load().stereo_damage_mask(plan.handle, _p(disp_t), float(delta_t), float(tau),
+                                         _p(out), _stream()))
+    return out
+
+
 # ---- differentiable form ----------------------------------------------------
 def _plane3(plane):
     vals = [float(x) for x in (plane.detach().cpu().tolist() if isinstance(plane, torch.Tensor)

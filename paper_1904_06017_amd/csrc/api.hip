@@ -382,4 +382,13 @@ stereo_status stereo_road_transform(stereo_plan_t plan, const float* disp,
   return STEREO_OK;
 }
 
+stereo_status stereo_damage_mask(stereo_plan_t plan, const float* disp_t, float delta_t,
+                                 float tau, uint8_t* mask, hipStream_t stream) {
+  STEREO_REQUIRE(plan && disp_t && mask, "plan, disp_t and mask must be non-NULL");
+  STEREO_REQUIRE(std::isfinite(delta_t) && std::isfinite(tau) && tau > 0.0f,
+                 "delta_t must be finite and tau finite and > 0");
+  STEREO_HIP(launch_damage_mask(plan->P, disp_t, delta_t, tau, mask, stream), "damage mask");
+  return STEREO_OK;
+}
+
 }  // extern "C"

@@ -193,6 +193,9 @@ hipError_t launch_lr_jobs(const LrJob* jobs, const int* first, int n, int blocks
 // Grad workspace layout for the plan (sets g_off / g_end); 0 for U8 plans.
 size_t grad_layout(Plan& P, size_t base);
 
+hipError_t launch_damage_mask(const Plan& P, const float* disp_t, float delta_t, float tau,
+                              uint8_t* mask, hipStream_t s);
+
 hipError_t launch_road(const Plan& P, const float* disp, const uint8_t* mask,
                        double psi0, double lambda0, double delta_psi,
                        int max_iter, float delta_t, stereo_road_fit* fit,

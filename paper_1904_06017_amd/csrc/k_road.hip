@@ -204,7 +204,26 @@ road_apply_kernel(const float* __restrict__ disp, int W, int H,
                    (double)delta_t);
 }
 
+// Damage below the flattened road: mask = finite(l') && l' < delta_t - tau.
+__global__ void __launch_bounds__(256)
+damage_mask_kernel(const float* __restrict__ disp_t, int64_t n, float level,
+                   uint8_t* __restrict__ mask) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float d = disp_t[i];
+  mask[i] = (isfinite(d) && d < level) ? 1 : 0;
+}
+
 }  // namespace
+
+hipError_t launch_damage_mask(const Plan& P, const float* disp_t, float delta_t, float tau,
+                              uint8_t* mask, hipStream_t s) {
+  const int64_t n = (int64_t)P.W * P.H;
+  const float level = delta_t - tau;
+  hipLaunchKernelGGL(damage_mask_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     disp_t, n, level, mask);
+  return hipGetLastError();
+}
 
 hipError_t launch_road(const Plan& P, const float* disp, const uint8_t* mask,
                        double psi0, double lambda0, double delta_psi, int max_iter,

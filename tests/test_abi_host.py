@@ -134,3 +134,17 @@ def test_status_strings(lib):
     for k, v in _lib.STATUS.items():
         assert lib.stereo_status_string(k).decode() == v
     assert b"gfx950" in lib.stereo_version()
+
+
+def test_damage_mask_argument_checks(lib):
+    p = make_params(64, 48, 16, delta_p=8, plane=(4, 0, 0.1))
+    s, h = _create(lib, p)
+    buf = ctypes.create_string_buffer(64)
+    # NULL pointers and a non-positive threshold are rejected before any launch
+    assert lib.stereo_damage_mask(h, None, ctypes.c_float(0.0), ctypes.c_float(0.5), buf,
+                                  None) == 1
+    assert lib.stereo_damage_mask(h, buf, ctypes.c_float(0.0), ctypes.c_float(0.0), buf,
+                                  None) == 1
+    assert lib.stereo_damage_mask(h, buf, ctypes.c_float(0.0), ctypes.c_float(float("nan")),
+                                  buf, None) == 1
+    lib.stereo_plan_destroy(h)

@@ -244,7 +244,7 @@ def _sample_pixels(W, H, n, seed):
     return sorted(pts)
 
 
-@pytest.mark.parametrize("name", ["c3a", "c3b", "c2"])
+@pytest.mark.parametrize("name", ["c3a", "c3b", "c2", "paper"])
 def test_full_size_sampled(name):
     w = workload(name)
     sc = make_workload_pair(w)
@@ -268,3 +268,41 @@ def test_full_size_sampled(name):
             assert bool(valid[v, u]) == q["valid"], (u, v)
             if q["valid"]:
                 assert abs(disp[v, u] - q["disp"]) <= tol, (u, v)
+
+
+def test_damage_mask_bit_exact():
+    """The damage-mask kernel against the oracle on the oracle's own
+    transformed map (rounded to FP32), with NaN, infinities and values at
+    the threshold planted in it; both decide in FP32."""
+    w = workload("c1")
+    sc = make_workload_pair(w)
+    o = OS.match(sc.ref, sc.tar, w)
+    _, dt = ORD.road_transform(o["disp"], o["valid"])
+    dt32 = dt.astype(np.float32)
+    dt32[0, :6] = [np.nan, np.inf, -np.inf, -0.5,
+                   np.nextafter(np.float32(-0.5), np.float32(-1.0)), 0.0]
+    plan = api.Plan.from_workload(w)
+    for delta_t, tau in ((0.0, 0.5), (3.0, 0.25), (0.0, 1e-3)):
+        g = _host(api.damage_mask(plan, _dev(dt32), delta_t, tau))
+        assert np.array_equal(g.astype(bool), ORD.damage_mask(dt32, delta_t, tau)), (delta_t, tau)
+
+
+def test_damage_segmentation_full_size():
+    """1280x720 pair through the GPU path (match, road transform, damage
+    mask): sanity bounds against the generator's ground truth."""
+    from oracle import metrics as OM
+    w = workload("c3a")
+    sc = make_workload_pair(w)
+    plan = api.Plan.from_workload(w)
+    out = api.match(plan, _dev(sc.ref), _dev(sc.tar))
+    fit, dt = api.road_transform(plan, out["disp"], out["valid"])
+    m = _host(api.damage_mask(plan, dt, 0.0, 0.5)).astype(bool)
+    vv, uu = np.mgrid[0:w.height, 0:w.width]
+    depth = w.plane[0] + w.plane[1] * uu + w.plane[2] * vv - sc.d_gt
+    r = w.ncc_radius + w.bil_radius
+    sel = np.zeros(sc.visible.shape, bool)
+    sel[r:-r, w.num_disp + r:-r] = True
+    sel &= sc.visible
+    print(f"[damage] iou {OM.iou(m, depth >= 0.5, sel):.3f}", flush=True)
+    assert OM.iou(m, depth >= 0.5, sel) >= 0.7
+    assert np.mean(m[sel & sc.road_mask]) <= 0.01

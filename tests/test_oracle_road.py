@@ -7,7 +7,11 @@ import numpy as np
 import pytest
 
 import oracle.road as RD
+import oracle.stereo as OS
 from oracle import metrics
+from synth import make_scene, workload
+
+OR, OM = RD, metrics
 
 
 def _rolled_points(rng, W=640, H=480, step=5, noise=0.3, psi=None, a1=None):
@@ -138,3 +142,50 @@ def test_wrap_into_half_open_interval():
         w = RD._wrap(x)
         assert -math.pi / 2 < w <= math.pi / 2
         assert abs(math.sin(2 * (w - x))) < 1e-12
+
+
+def test_damage_mask_threshold_rule():
+    """Hand-built FP32 values around the level delta_t - tau (Sec. 4.4.3)."""
+    dt = np.array([[0.0, -0.49, -0.5, -0.51, np.nan],
+                   [-np.inf, np.inf, 1.0, -3.0, np.float32(-0.5) - np.float32(1e-7)]],
+                  np.float32)
+    m = OR.damage_mask(dt, 0.0, 0.5)
+    assert m.tolist() == [[False, False, False, True, False],
+                          [False, False, False, True, True]]
+    # delta_t shifts the level; the comparison is strict
+    assert OR.damage_mask(np.float32([[2.5]]), 3.0, 0.5).tolist() == [[False]]
+    assert OR.damage_mask(np.float32([[2.49]]), 3.0, 0.5).tolist() == [[True]]
+
+
+def test_iou_small_cases():
+    a = np.array([[1, 1, 0], [0, 0, 0]], bool)
+    b = np.array([[0, 1, 1], [0, 0, 0]], bool)
+    assert OM.iou(a, b) == pytest.approx(1.0 / 3.0)
+    assert OM.iou(a, a) == 1.0
+    assert OM.iou(a, ~a) == 0.0
+    assert OM.iou(np.zeros((2, 2), bool), np.zeros((2, 2), bool)) == 1.0
+    sel = np.array([[1, 1, 0], [1, 1, 1]], bool)      # drops the disagreeing pixel
+    assert OM.iou(a, b, sel) == pytest.approx(0.5)
+
+
+@pytest.mark.parametrize("seed,npot,ncr", [(11, 6, 2), (12, 4, 1), (13, 0, 0)])
+def test_damage_segmentation_on_synthetic_roads(seed, npot, ncr):
+    """Sanity bounds against the generator's ground truth, not parity: on
+    interior visible pixels the damage found at tau = 0.5 overlaps the
+    region deeper than tau with IoU >= 0.75, and plain road is almost never
+    flagged; a scene without damage gives an empty mask."""
+    w = workload("c1")
+    sc = make_scene(w.width, w.height, w.plane, npot, ncr, seed)
+    o = OS.match(sc.ref, sc.tar, w)
+    fit, dt = OR.road_transform(o["disp"], o["valid"])
+    vv, uu = np.mgrid[0:w.height, 0:w.width]
+    depth = w.plane[0] + w.plane[1] * uu + w.plane[2] * vv - sc.d_gt
+    r = w.ncc_radius + w.bil_radius
+    sel = np.zeros(sc.visible.shape, bool)
+    sel[r:-r, w.num_disp + r:-r] = True
+    sel &= sc.visible
+    m = OR.damage_mask(dt, 0.0, 0.5)
+    assert OM.iou(m, depth >= 0.5, sel) >= 0.75
+    assert np.mean(m[sel & sc.road_mask]) <= 0.005
+    if npot == 0 and ncr == 0:
+        assert not m[sel].any()
