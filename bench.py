@@ -69,14 +69,74 @@ def _gen(w):
 
 
 def batch_scenes():
-    """The 64 seeded pairs of the mixed batch, generated on host cores (a
-    process pool started before the GPU is touched)."""
+    """The 64 seeded pairs of the mixed batch and the tracking sequence,
+    generated on host cores (a process pool started before the GPU is
+    touched)."""
     import multiprocessing as mp
     from synth import batch_workloads
     ws = batch_workloads()
     with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        seq = pool.apply_async(sequence_frames)
         imgs = pool.map(_gen, ws)
-    return ws, imgs
+        seq = seq.get()
+    return (ws, imgs), seq
+
+
+def sequence_frames():
+    """4 frames of a 1280x720 road whose plane drifts (slope, roll, offset)."""
+    from synth import road_sequence, workload
+    w = workload("c3a")
+    return w, road_sequence(w.width, w.height, 4, seed=31, n_potholes=w.n_potholes,
+                            n_cracks=w.n_cracks)
+
+
+def closed_loop(args, seq):
+    """Plane tracking over a frame sequence: bootstrap with a full-range pass
+    (128 levels, no warp) on frame 0, then each frame matched with the plane
+    fitted on the previous one (device-resident state, no host sync)."""
+    from dataclasses import replace
+
+    import numpy as np
+    import torch
+
+    from paper_1904_06017_amd import api
+    w, frames = seq
+    dev = torch.device("cuda:0")
+    imgs = [(torch.from_numpy(sc.ref).to(dev), torch.from_numpy(sc.tar).to(dev))
+            for _, _, sc in frames]
+    raw = api.Plan.from_workload(replace(w, perspective=False, delta_p=0.0, num_disp=128))
+    m = api.match(raw, *imgs[0])
+    fit0, _ = api.road_transform(raw, m["disp"], m["valid"])
+    tr = api.PlaneTracker(api.Plan.from_workload(w))
+    out = None
+    for _ in range(2):                               # warm-up passes over the sequence
+        tr.init_from_fit(fit0)
+        for ref, tar in imgs[1:]:
+            out = tr.step(ref, tar, out=out)
+    reps = max(3, args.steps // 10)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    t = 0.0
+    errs = []
+    vv, uu = np.mgrid[0:w.height, 0:w.width]
+    for rep in range(reps):
+        tr.init_from_fit(fit0)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for ref, tar in imgs[1:]:
+            out = tr.step(ref, tar, out=out)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t += ev[0].elapsed_time(ev[1])
+    # plane error of the last pass, frame by frame (re-run with reads)
+    tr.init_from_fit(fit0)
+    for (c, _, _), (ref, tar) in zip(frames[1:], imgs[1:]):
+        tr.step(ref, tar, out=out)
+        p = tr.read()["plane"]
+        errs.append(float(np.max(np.abs((p[0] - c[0]) + (p[1] - c[1]) * uu + (p[2] - c[2]) * vv))))
+    n = len(imgs) - 1
+    return dict(frames=n, workload=w.name, bootstrap_levels=128,
+                ms_per_tracked_frame=round(t / reps / n, 4),
+                max_road_disparity_error_px=[round(e, 4) for e in errs])
 
 
 def batched(args, scenes):
@@ -130,7 +190,7 @@ def batched(args, scenes):
 
 
 def run(args):
-    scenes = batch_scenes() if args.extra else None
+    scenes, seq = batch_scenes() if args.extra else (None, None)
     import torch
 
     from paper_1904_06017_amd import api
@@ -239,6 +299,7 @@ def run(args):
         res["range_reduction"] = range_reduction(args, sc, ms)
         res["fwd_bwd"] = fwd_bwd(args)
         res["paper_preset"] = paper_preset(args)
+        res["closed_loop"] = closed_loop(args, seq)
         res["batched"] = batched(args, scenes)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, sc, args.cpu_rows)

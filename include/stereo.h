@@ -206,6 +206,40 @@ stereo_status stereo_road_transform(stereo_plan_t plan, const float* disp,
                                     void* ws, size_t ws_bytes,
                                     hipStream_t stream);
 
+/* ---- closed-loop plane tracking over a frame sequence ----------------------
+ * The road fit of frame t (Sec. 3.3) gives the plane c = (alpha0,
+ * -alpha1 sin psi, alpha1 cos psi) that frame t+1's perspective
+ * transformation (Sec. 3.1) and shift back use, and its psi warm-starts frame
+ * t+1's fit (the paper seeds each fit from the previous estimate).  The state
+ * lives in device memory, so a tracked frame needs no host synchronisation
+ * and can be captured in a graph.  The caller initialises it (for instance
+ * from a fit of a full-range pass without the perspective transformation:
+ * copy stereo_road_fit.plane and .psi, frames = 0). */
+typedef struct {
+  double plane[3];   /* (c0, c1, c2): the plane the next frame is matched with  */
+  double psi;        /* warm start of the next roll fit                        */
+  int32_t frames;    /* fits folded into the state so far                      */
+  int32_t pad_;
+} stereo_plane_state;   /* 40 bytes */
+
+/* stereo_match with the plane of *state_dev (device memory) in place of the
+ * plan's; the plan must have perspective = 1 (its delta_p, ranges and radii
+ * apply).  Outputs and workspace as stereo_match. */
+stereo_status stereo_match_tracked(stereo_plan_t plan, const void* ref, const void* tar,
+                                   const stereo_plane_state* state_dev, int16_t* dint_R,
+                                   int16_t* dint_T, float* dsub, uint8_t* valid, float* disp,
+                                   void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* stereo_road_transform with psi_init = state_dev->psi; afterwards, if the
+ * fit is not flat (>= 3 points and |alpha1| >= 1e-6), the state takes the
+ * fitted plane and psi and frames += 1; otherwise it is left unchanged. */
+stereo_status stereo_road_transform_tracked(stereo_plan_t plan, const float* disp,
+                                            const uint8_t* mask, double lambda0,
+                                            double delta_psi, int32_t max_iter,
+                                            float delta_t, stereo_plane_state* state_dev,
+                                            stereo_road_fit* fit_dev, float* disp_t,
+                                            void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- road damage on the transformed map, Sec. 4.4.3 -----------------------
  * After Eq. (29) the road surface is flat at delta_t and damage (potholes,
  * cracks: farther away, smaller disparity) lies below it.  Writes

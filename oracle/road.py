@@ -164,6 +164,12 @@ def transform(disp, fit: RoadFit, delta_t=0.0):
             + delta_t)
 
 
+def plane_from_fit(fit: RoadFit):
+    """The road model of the fit, d = a0 + a1 (v cos psi - u sin psi), as the
+    plane c = (c0, c1, c2) of d_road = c0 + c1 u + c2 v (Sec. 3.1 / 3.3)."""
+    return (fit.alpha0, -fit.alpha1 * math.sin(fit.psi), fit.alpha1 * math.cos(fit.psi))
+
+
 def damage_mask(disp_t, delta_t=0.0, tau=0.5):
     """Damage on the transformed map (Sec. 4.4.3): after Eq. (29) the road is
     flat at delta_t and potholes / cracks (farther away, smaller disparity)

@@ -43,6 +43,11 @@ class RoadFit(Structure):
     ]
 
 
+class PlaneState(Structure):
+    _fields_ = [("plane", c_double * 3), ("psi", c_double), ("frames", c_int32),
+                ("pad_", c_int32)]
+
+
 class BatchItem(Structure):
     _fields_ = [("plan", c_void_p), ("ref", c_void_p), ("tar", c_void_p),
                 ("dint_R", c_void_p), ("valid", c_void_p), ("disp", c_void_p)]
@@ -81,6 +86,12 @@ SIGNATURES = {
     "stereo_road_transform": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double,
                                       c_double, c_int32, c_float, c_void_p, c_void_p,
                                       c_void_p, c_size_t, c_void_p]),
+    "stereo_match_tracked": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                                     c_void_p]),
+    "stereo_road_transform_tracked": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double,
+                                              c_int32, c_float, c_void_p, c_void_p, c_void_p,
+                                              c_void_p, c_size_t, c_void_p]),
     "stereo_damage_mask": (c_int, [c_void_p, c_void_p, c_float, c_float, c_void_p, c_void_p]),
     "stereo_soft_forward": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_double), c_void_p,
                                     c_void_p, c_void_p, c_size_t, c_void_p]),

@@ -12,7 +12,7 @@ from typing import Optional
 import torch
 
 from . import _lib
-from ._lib import RoadFit, StereoParams, check
+from ._lib import PlaneState, RoadFit, StereoParams, check
 
 DELTA_PSI = math.pi / 1.8e6
 LAMBDA0 = 10.0
@@ -232,6 +232,70 @@ def road_transform(plan: Plan, disp, mask=None, psi_init=0.0, lambda0=LAMBDA0,
         int(max_iter), float(delta_t), _p(fit_buf), _p(out), _p(ws), plan.workspace_bytes,
         _stream()))
     return (road_fit_from_bytes(fit_buf) if read_fit else fit_buf), out
+
+
+class PlaneTracker:
+    """Closed-loop plane estimation over a frame sequence: each frame is
+    matched with the plane fitted on the previous one (state in device
+    memory, no host synchronisation per frame).  Initialise with set() or
+    init_from_fit() (e.g. the fit of a full-range pass without the warp)."""
+
+    def __init__(self, plan: Plan, device="cuda"):
+        if not plan.params.perspective:
+            raise ValueError("tracking needs a plan with perspective = 1")
+        self.plan = plan
+        self.state = torch.zeros(ctypes.sizeof(PlaneState), dtype=torch.uint8, device=device)
+        self.fit_buf = torch.zeros(ctypes.sizeof(RoadFit), dtype=torch.uint8, device=device)
+
+    def set(self, plane, psi=0.0, frames=0):
+        st = PlaneState()
+        for k in range(3):
+            st.plane[k] = float(plane[k])
+        st.psi = float(psi)
+        st.frames = int(frames)
+        host = torch.frombuffer(bytearray(bytes(st)), dtype=torch.uint8)
+        self.state.copy_(host)
+
+    def init_from_fit(self, fit: dict):
+        self.set(fit["plane"], fit["psi"], 0)
+
+    def read(self) -> dict:
+        st = PlaneState.from_buffer_copy(bytes(self.state.cpu().numpy().tobytes()))
+        return dict(plane=tuple(st.plane), psi=st.psi, frames=st.frames)
+
+    def step(self, ref, tar, out=None, disp_t=None, delta_t=0.0, lambda0=LAMBDA0,
+             delta_psi=DELTA_PSI, max_iter=100, want_target=False):
+        """Match with the current plane, then fit and fold the new plane in.
+        Returns the match outputs plus disp_t (transformed map)."""
+        plan = self.plan
+        _need(ref, plan.img_dtype, (plan.H, plan.W), "ref")
+        _need(tar, plan.img_dtype, (plan.H, plan.W), "tar")
+        dev = ref.device
+        if out is None:
+            out = dict(
+                dint_R=torch.empty((plan.H, plan.W), dtype=torch.int16, device=dev),
+                dsub=torch.empty((plan.H, plan.W), dtype=torch.float32, device=dev),
+                valid=torch.empty((plan.H, plan.W), dtype=torch.uint8, device=dev),
+                disp=torch.empty((plan.H, plan.W), dtype=torch.float32, device=dev))
+            if want_target:
+                out["dint_T"] = torch.empty((plan.H, plan.W), dtype=torch.int16, device=dev)
+        if disp_t is None:
+            disp_t = out.get("disp_t")
+            if disp_t is None:
+                disp_t = torch.empty((plan.H, plan.W), dtype=torch.float32, device=dev)
+        ws = plan.workspace(dev)
+        lib = _lib.load()
+        check(lib.stereo_match_tracked(plan.handle, _p(ref), _p(tar), _p(self.state),
+                                       _p(out["dint_R"]), _p(out.get("dint_T")),
+                                       _p(out["dsub"]), _p(out["valid"]), _p(out["disp"]),
+                                       _p(ws), plan.workspace_bytes, _stream()))
+        check(lib.stereo_road_transform_tracked(plan.handle, _p(out["disp"]), _p(out["valid"]),
+                                                float(lambda0), float(delta_psi), int(max_iter),
+                                                float(delta_t), _p(self.state),
+                                                _p(self.fit_buf), _p(disp_t), _p(ws),
+                                                plan.workspace_bytes, _stream()))
+        out["disp_t"] = disp_t
+        return out
 
 
 def damage_mask(plan: Plan, disp_t, delta_t=0.0, tau=0.5, out=None):

@@ -298,10 +298,15 @@ stereo_status stereo_match(stereo_plan_t plan, const void* ref, const void* tar,
                                nullptr, stream);
 }
 
-stereo_status stereo_match_profiled(stereo_plan_t plan, const void* ref, const void* tar,
-                                    int16_t* dint_R, int16_t* dint_T, float* dsub,
-                                    uint8_t* valid, float* disp, void* ws, size_t ws_bytes,
-                                    hipEvent_t* ev, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// The plain forward; st (nullable) supplies the plane from device memory.
+stereo_status match_impl(stereo_plan_t plan, const void* ref, const void* tar,
+                         const stereo_plane_state* st, int16_t* dint_R, int16_t* dint_T,
+                         float* dsub, uint8_t* valid, float* disp, void* ws, size_t ws_bytes,
+                         hipEvent_t* ev, hipStream_t stream) {
   STEREO_REQUIRE(plan && ref && tar && dint_R, "plan, ref, tar and dint_R must be non-NULL");
   const Plan& P = plan->P;
   stereo_status s = check_ws(P, ws, ws_bytes);
@@ -316,7 +321,8 @@ stereo_status stereo_match_profiled(stereo_plan_t plan, const void* ref, const v
   };
 
   STEREO_HIP(mark(0), "event record");
-  STEREO_HIP(launch_warp(P, tar, tarw, stream), "warp");
+  STEREO_HIP(st ? launch_warp_tracked(P, tar, st, tarw, stream)
+                : launch_warp(P, tar, tarw, stream), "warp");
   STEREO_HIP(mark(1), "event record");
   STEREO_HIP(launch_block_stats(P, ref, P.p.dtype, P.p.pitch_ref, m.zX, m.isdX, stream),
              "block statistics (ref)");
@@ -357,10 +363,34 @@ stereo_status stereo_match_profiled(stereo_plan_t plan, const void* ref, const v
   }
   STEREO_HIP(mark(5), "event record");
   if (valid || disp)
-    STEREO_HIP(launch_lr_check(P, dint_R, lr ? dT : nullptr, ds, valid, disp, stream),
+    STEREO_HIP(st ? launch_lr_check_tracked(P, dint_R, lr ? dT : nullptr, ds, st, valid, disp,
+                                            stream)
+                  : launch_lr_check(P, dint_R, lr ? dT : nullptr, ds, valid, disp, stream),
                "left-right check");
   STEREO_HIP(mark(6), "event record");
   return STEREO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+stereo_status stereo_match_profiled(stereo_plan_t plan, const void* ref, const void* tar,
+                                    int16_t* dint_R, int16_t* dint_T, float* dsub,
+                                    uint8_t* valid, float* disp, void* ws, size_t ws_bytes,
+                                    hipEvent_t* ev, hipStream_t stream) {
+  return match_impl(plan, ref, tar, nullptr, dint_R, dint_T, dsub, valid, disp, ws, ws_bytes,
+                    ev, stream);
+}
+
+stereo_status stereo_match_tracked(stereo_plan_t plan, const void* ref, const void* tar,
+                                   const stereo_plane_state* state_dev, int16_t* dint_R,
+                                   int16_t* dint_T, float* dsub, uint8_t* valid, float* disp,
+                                   void* ws, size_t ws_bytes, hipStream_t stream) {
+  STEREO_REQUIRE(plan && state_dev, "plan and state_dev must be non-NULL");
+  STEREO_REQUIRE(plan->P.p.perspective == 1, "tracking needs a plan with perspective = 1");
+  return match_impl(plan, ref, tar, state_dev, dint_R, dint_T, dsub, valid, disp, ws, ws_bytes,
+                    nullptr, stream);
 }
 
 stereo_status stereo_road_transform(stereo_plan_t plan, const float* disp,
@@ -379,6 +409,26 @@ stereo_status stereo_road_transform(stereo_plan_t plan, const float* disp,
   STEREO_HIP(launch_road(P, disp, mask, psi_init, lambda0, delta_psi, max_iter, delta_t,
                          fit_dev, disp_t, at<double>(ws, P.off_road), stream),
              "road transform");
+  return STEREO_OK;
+}
+
+stereo_status stereo_road_transform_tracked(stereo_plan_t plan, const float* disp,
+                                            const uint8_t* mask, double lambda0,
+                                            double delta_psi, int32_t max_iter,
+                                            float delta_t, stereo_plane_state* state_dev,
+                                            stereo_road_fit* fit_dev, float* disp_t,
+                                            void* ws, size_t ws_bytes, hipStream_t stream) {
+  STEREO_REQUIRE(plan && disp && fit_dev && state_dev,
+                 "plan, disp, fit_dev and state_dev must be non-NULL");
+  STEREO_REQUIRE(max_iter >= 1, "max_iter must be >= 1");
+  STEREO_REQUIRE(lambda0 > 0.0 && std::isfinite(lambda0), "lambda0 must be finite and > 0");
+  STEREO_REQUIRE(delta_psi > 0.0, "delta_psi must be > 0");
+  const Plan& P = plan->P;
+  stereo_status s = check_ws(P, ws, ws_bytes);
+  if (s != STEREO_OK) return s;
+  STEREO_HIP(launch_road(P, disp, mask, 0.0, lambda0, delta_psi, max_iter, delta_t, fit_dev,
+                         disp_t, at<double>(ws, P.off_road), stream, state_dev),
+             "road transform (tracked)");
   return STEREO_OK;
 }
 

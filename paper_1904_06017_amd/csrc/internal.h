@@ -69,6 +69,9 @@ Consts consts_of(const Plan& P);
 // ---- kernel launchers (each returns hipGetLastError after the launch) ----
 hipError_t launch_warp(const Plan& P, const void* tar, float* tar_w,
                        hipStream_t s);
+// the same with the plane read from device memory (perspective plans)
+hipError_t launch_warp_tracked(const Plan& P, const void* tar, const stereo_plane_state* st,
+                               float* tar_w, hipStream_t s);
 
 // z = mu / sigma and isd = 1 / sigma of (I - 128) over the clamped (2r+1)^2
 // block centred at every column x in [-r, W + r) and row y; a flat block
@@ -142,6 +145,9 @@ hipError_t launch_wta(const Plan& P, const float* E, int16_t* dint,
 hipError_t launch_lr_check(const Plan& P, const int16_t* dR, const int16_t* dT,
                            const float* dsub, uint8_t* valid, float* disp,
                            hipStream_t s);
+hipError_t launch_lr_check_tracked(const Plan& P, const int16_t* dR, const int16_t* dT,
+                                   const float* dsub, const stereo_plane_state* st,
+                                   uint8_t* valid, float* disp, hipStream_t s);
 
 // ---- batched stages: one launch covers every job of a list.  Job j owns
 // blocks [first[j], first[j+1]) of the launch (first[0] = 0, first[n] = the
@@ -199,7 +205,8 @@ hipError_t launch_damage_mask(const Plan& P, const float* disp_t, float delta_t,
 hipError_t launch_road(const Plan& P, const float* disp, const uint8_t* mask,
                        double psi0, double lambda0, double delta_psi,
                        int max_iter, float delta_t, stereo_road_fit* fit,
-                       float* disp_t, double* partials, hipStream_t s);
+                       float* disp_t, double* partials, hipStream_t s,
+                       stereo_plane_state* state = nullptr);
 
 }  // namespace stereo
 

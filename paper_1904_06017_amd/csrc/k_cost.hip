@@ -54,6 +54,14 @@ warp_kernel(const T* __restrict__ tar, int64_t pitch, int W, int H,
   warp_body<T>(tar, pitch, W, delta_p, c0, c1, c2, persp, out, blockIdx.x, blockIdx.y);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256)
+warp_tracked_kernel(const T* __restrict__ tar, int64_t pitch, int W, double delta_p,
+                    const stereo_plane_state* __restrict__ st, float* __restrict__ out) {
+  warp_body<T>(tar, pitch, W, delta_p, st->plane[0], st->plane[1], st->plane[2], 1, out,
+               blockIdx.x, blockIdx.y);
+}
+
 // Block statistics.  One workgroup covers 64 block centres x 16 rows; the
 // clamped input tile (16 + 2r rows x 64 + 2r columns, offset by -128) is
 // staged in LDS, then each thread forms the mean and the population
@@ -474,6 +482,19 @@ hipError_t launch_warp(const Plan& P, const void* tar, float* tar_w, hipStream_t
     hipLaunchKernelGGL(warp_kernel<float>, grid, dim3(256), 0, s,
                        (const float*)tar, p.pitch_tar, P.W, P.H, dp, p.plane[0],
                        p.plane[1], p.plane[2], p.perspective, tar_w);
+  return hipGetLastError();
+}
+
+hipError_t launch_warp_tracked(const Plan& P, const void* tar, const stereo_plane_state* st,
+                               float* tar_w, hipStream_t s) {
+  dim3 grid((P.W + 255) / 256, P.H);
+  const double dp = (double)P.p.delta_p;
+  if (P.p.dtype == STEREO_U8)
+    hipLaunchKernelGGL(warp_tracked_kernel<uint8_t>, grid, dim3(256), 0, s,
+                       (const uint8_t*)tar, P.p.pitch_tar, P.W, dp, st, tar_w);
+  else
+    hipLaunchKernelGGL(warp_tracked_kernel<float>, grid, dim3(256), 0, s,
+                       (const float*)tar, P.p.pitch_tar, P.W, dp, st, tar_w);
   return hipGetLastError();
 }
 

@@ -106,7 +106,7 @@ __device__ double wrap_half_pi(double psi) {
 __global__ void __launch_bounds__(kRoadThreads)
 road_fit_kernel(const double* __restrict__ partials, int nblocks, int W, int H,
                 double psi0, double lambda0, double delta_psi, int max_iter,
-                stereo_road_fit* __restrict__ out) {
+                stereo_road_fit* __restrict__ out, stereo_plane_state* __restrict__ state) {
   __shared__ double red[kMom][kRoadThreads];
   double a[kMom];
 #pragma unroll
@@ -126,6 +126,7 @@ road_fit_kernel(const double* __restrict__ partials, int nblocks, int W, int H,
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
+  if (state) psi0 = state->psi;            // warm start from the previous frame
   double mom[kMom];
 #pragma unroll
   for (int j = 0; j < kMom; ++j) mom[j] = red[j][0];
@@ -188,6 +189,13 @@ road_fit_kernel(const double* __restrict__ partials, int nblocks, int W, int H,
   r.converged = converged;
   r.flat = flat;
   *out = r;
+  if (state && !flat) {                    // the next frame's plane
+    state->plane[0] = r.plane[0];
+    state->plane[1] = r.plane[1];
+    state->plane[2] = r.plane[2];
+    state->psi = psi;
+    state->frames += 1;
+  }
 }
 
 // Eq. (29): l' = l - a0 + a1 (u sin psi - v cos psi) + delta_t.
@@ -228,13 +236,13 @@ hipError_t launch_damage_mask(const Plan& P, const float* disp_t, float delta_t,
 hipError_t launch_road(const Plan& P, const float* disp, const uint8_t* mask,
                        double psi0, double lambda0, double delta_psi, int max_iter,
                        float delta_t, stereo_road_fit* fit, float* disp_t,
-                       double* partials, hipStream_t s) {
+                       double* partials, hipStream_t s, stereo_plane_state* state) {
   hipLaunchKernelGGL(road_moments_kernel, dim3(P.road_blocks), dim3(kRoadThreads), 0, s,
                      disp, mask, P.W, P.H, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(road_fit_kernel, dim3(1), dim3(kRoadThreads), 0, s, partials, P.road_blocks,
-                     P.W, P.H, psi0, lambda0, delta_psi, max_iter, fit);
+                     P.W, P.H, psi0, lambda0, delta_psi, max_iter, fit, state);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (disp_t) {

@@ -70,6 +70,15 @@ lr_kernel(const int16_t* __restrict__ dR, const int16_t* __restrict__ dT,
           blockIdx.x, blockIdx.y);
 }
 
+__global__ void __launch_bounds__(256)
+lr_tracked_kernel(const int16_t* __restrict__ dR, const int16_t* __restrict__ dT,
+                  const float* __restrict__ dsub, int W, float lr_delta, int use_lr,
+                  double delta_p, const stereo_plane_state* __restrict__ st,
+                  uint8_t* __restrict__ valid, float* __restrict__ disp) {
+  lr_body(dR, dT, dsub, W, lr_delta, use_lr, 1, delta_p, st->plane[0], st->plane[1],
+          st->plane[2], valid, disp, blockIdx.x, blockIdx.y);
+}
+
 __device__ __forceinline__ int job_of(const int* __restrict__ first, int n, int b) {
   int lo = 0, hi = n;
   while (hi - lo > 1) {
@@ -117,6 +126,16 @@ hipError_t launch_lr_jobs(const LrJob* jobs, const int* first, int n, int blocks
                           hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(lr_jobs_kernel, dim3(blocks), dim3(256), 0, s, jobs, first, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_lr_check_tracked(const Plan& P, const int16_t* dR, const int16_t* dT,
+                                   const float* dsub, const stereo_plane_state* st,
+                                   uint8_t* valid, float* disp, hipStream_t s) {
+  const stereo_params& p = P.p;
+  hipLaunchKernelGGL(lr_tracked_kernel, dim3((P.W + 255) / 256, P.H), dim3(256), 0, s, dR, dT,
+                     dsub, P.W, p.lr_delta, (p.lr_check && dT) ? 1 : 0, (double)p.delta_p, st,
+                     valid, disp);
   return hipGetLastError();
 }
 

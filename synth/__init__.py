@@ -7,7 +7,7 @@ any computation.
 """
 from .presets import (Workload, WORKLOADS, workload, batch_workloads,
                       crop_workload)
-from .scenes import Scene, make_scene, make_workload_pair
+from .scenes import Scene, make_scene, make_workload_pair, road_sequence
 
-__all__ = ["Workload", "WORKLOADS", "workload", "batch_workloads",
+__all__ = ["road_sequence", "Workload", "WORKLOADS", "workload", "batch_workloads",
            "crop_workload", "Scene", "make_scene", "make_workload_pair"]

@@ -164,3 +164,27 @@ def make_scene(width, height, plane, n_potholes, n_cracks, seed,
 def make_workload_pair(w: Workload) -> Scene:
     return make_scene(w.width, w.height, w.true_plane, w.n_potholes,
                       w.n_cracks, w.seed, float_images=(w.dtype == "f32"))
+
+
+def road_sequence(width, height, n_frames, seed, n_potholes=4, n_cracks=1, slope=0.1,
+                  psi0_deg=2.0, dpsi_deg=0.4, da0=0.25, dslope=0.01, float_images=False):
+    """Frames of a road whose plane drifts slowly (a vehicle moving on it):
+    slope a1_t = slope (1 + dslope t) px/row, roll psi_t = psi0 + dpsi t
+    degrees, offset a0_t = a0 + da0 t px with a0 chosen so that the smallest
+    road disparity of frame 0 is 4 px; plane c_t = (a0_t, -a1_t sin psi_t,
+    a1_t cos psi_t).  Each frame has its own damage and texture, seeded from
+    SeedSequence(seed).  Returns [(plane, psi_rad, Scene)] per frame."""
+    kids = np.random.SeedSequence(seed).spawn(n_frames)
+    psi0 = math.radians(psi0_deg)
+    ys = [v * math.cos(psi0) - u * math.sin(psi0)
+          for u in (0.0, width - 1.0) for v in (0.0, height - 1.0)]
+    a0 = 4.0 - slope * min(ys)
+    out = []
+    for t in range(n_frames):
+        psi = math.radians(psi0_deg + dpsi_deg * t)
+        a1 = slope * (1.0 + dslope * t)
+        c = (a0 + da0 * t, -a1 * math.sin(psi), a1 * math.cos(psi))
+        s = int(kids[t].generate_state(1)[0])
+        out.append((c, psi, make_scene(width, height, c, n_potholes, n_cracks, s,
+                                       float_images=float_images)))
+    return out

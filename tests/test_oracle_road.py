@@ -189,3 +189,45 @@ def test_damage_segmentation_on_synthetic_roads(seed, npot, ncr):
     assert np.mean(m[sel & sc.road_mask]) <= 0.005
     if npot == 0 and ncr == 0:
         assert not m[sel].any()
+
+
+def test_plane_from_fit_closed_form():
+    """An exact rolled planar disparity map: the fit's plane is the map's."""
+    c = (7.5, -0.012, 0.094)
+    vv, uu = np.mgrid[0:120, 0:160].astype(float)
+    d = c[0] + c[1] * uu + c[2] * vv
+    fit, _ = RD.road_transform(d)
+    # the descent stops within its step tolerance delta_psi of the roll
+    assert abs(fit.psi - math.atan(-c[1] / c[2])) <= 10 * RD.DELTA_PSI
+    p = RD.plane_from_fit(fit)
+    err = (p[0] - c[0]) + (p[1] - c[1]) * uu + (p[2] - c[2]) * vv
+    assert np.max(np.abs(err)) <= 1e-4
+
+
+def test_closed_loop_tracks_a_drifting_road():
+    """Frame t matched with the plane fitted on frame t-1 (bootstrap: a
+    full-range pass without the perspective transformation on frame 0)
+    follows a slowly drifting plane and keeps road pixels accurate
+    (sanity bounds against ground truth)."""
+    from dataclasses import replace
+    from synth import road_sequence
+    w = workload("c1")
+    seq = road_sequence(w.width, w.height, 4, seed=21)
+    wr = replace(w, perspective=False, delta_p=0.0, num_disp=48)
+    _, _, sc0 = seq[0]
+    o = OS.match(sc0.ref, sc0.tar, wr)
+    fit, _ = RD.road_transform(o["disp"], o["valid"])
+    plane, psi = RD.plane_from_fit(fit), fit.psi
+    vv, uu = np.mgrid[0:w.height, 0:w.width]
+    r = w.ncc_radius + w.bil_radius
+    for c, psi_true, sc in seq[1:]:
+        o = OS.match(sc.ref, sc.tar, replace(w, plane=tuple(plane)))
+        sel = np.zeros(sc.visible.shape, bool)
+        sel[r:-r, w.num_disp + r:-r] = True
+        sel &= sc.visible & sc.road_mask & np.isfinite(o["disp"])
+        assert metrics.error_pixel_percent(o["disp"], sc.d_gt, 1.0, sel) <= 1.0
+        fit, _ = RD.road_transform(o["disp"], o["valid"], psi0=psi)
+        plane, psi = RD.plane_from_fit(fit), fit.psi
+        err = (plane[0] - c[0]) + (plane[1] - c[1]) * uu + (plane[2] - c[2]) * vv
+        assert np.max(np.abs(err)) <= 0.3
+        assert abs(psi - psi_true) <= math.radians(0.5)
