@@ -77,9 +77,11 @@ def batch_scenes():
     ws = batch_workloads()
     with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
         seq = pool.apply_async(sequence_frames)
+        sk = pool.apply_async(skewed_frames)
         imgs = pool.map(_gen, ws)
         seq = seq.get()
-    return (ws, imgs), seq
+        sk = sk.get()
+    return (ws, imgs), (seq, sk)
 
 
 def sequence_frames():
@@ -88,6 +90,58 @@ def sequence_frames():
     w = workload("c3a")
     return w, road_sequence(w.width, w.height, 4, seed=31, n_potholes=w.n_potholes,
                             n_cracks=w.n_cracks)
+
+
+def skewed_frames():
+    """The 1280x720 pair re-imaged by a target camera rotated 0.3 degrees and
+    shifted 0.8 rows (a rig outside the rectified hypotheses)."""
+    from synth import skewed_pair, workload
+    w = workload("c3a")
+    sc, tar2, _, Hm, dtrue = skewed_pair(w)
+    return w, sc, tar2, Hm, dtrue
+
+
+def skewed_rig(args, sk):
+    """Matching the skewed pair through the general homography (Eq. 3) vs the
+    row shift of the plane: time per match and error pixels (> 1 px) against
+    the generator's ground truth on interior visible pixels."""
+    from dataclasses import replace
+
+    import numpy as np
+    import torch
+
+    from paper_1904_06017_amd import api
+    w, sc, tar2, Hm, dtrue = sk
+    dev = torch.device("cuda:0")
+    ref = torch.from_numpy(sc.ref).to(dev)
+    tar = torch.from_numpy(tar2).to(dev)
+    r = w.ncc_radius + w.bil_radius
+    sel = np.zeros(sc.visible.shape, bool)
+    sel[r:-r, w.num_disp + r:-r] = True
+    sel &= sc.visible
+    res = {}
+    for name, wk in (("homography", replace(w, homography=tuple(Hm.ravel()))), ("row_shift", w)):
+        plan = api.Plan.from_workload(wk)
+        o = None
+        for _ in range(3):
+            o = api.match(plan, ref, tar, out=o)
+        torch.cuda.synchronize()
+        n = max(10, args.steps // 2)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(n):
+            api.match(plan, ref, tar, out=o)
+        b.record()
+        torch.cuda.synchronize()
+        disp = o["disp"].cpu().numpy()
+        fin = sel & np.isfinite(disp)
+        err = np.abs(disp[fin] - dtrue[fin])
+        res[name] = dict(match_ms=round(a.elapsed_time(b) / n, 4),
+                         error_pixels_pct=round(float(np.mean(err > 1.0) * 100), 3),
+                         rms_px=round(float(np.sqrt(np.mean(err ** 2))), 4),
+                         valid_fraction=round(float(fin.sum() / sel.sum()), 4))
+    return dict(workload=w.name, rotation_deg=0.3, row_offset=0.8, **res)
 
 
 def closed_loop(args, seq):
@@ -190,7 +244,7 @@ def batched(args, scenes):
 
 
 def run(args):
-    scenes, seq = batch_scenes() if args.extra else (None, None)
+    scenes, (seq, sk) = batch_scenes() if args.extra else (None, (None, None))
     import torch
 
     from paper_1904_06017_amd import api
@@ -300,6 +354,7 @@ def run(args):
         res["fwd_bwd"] = fwd_bwd(args)
         res["paper_preset"] = paper_preset(args)
         res["closed_loop"] = closed_loop(args, seq)
+        res["skewed_rig"] = skewed_rig(args, sk)
         res["batched"] = batched(args, scenes)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, sc, args.cpu_rows)

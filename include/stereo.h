@@ -107,6 +107,20 @@ stereo_status stereo_plan_destroy(stereo_plan_t plan);
 stereo_status stereo_plan_workspace_bytes(stereo_plan_t plan, size_t* bytes);
 stereo_status stereo_plan_get_params(stereo_plan_t plan, stereo_params* out);
 
+/* ---- general homography warp, Eq. (3) (host only) ----------------------------
+ * Replaces the row shift of the plan's plane by the full homography H
+ * (row-major 3x3, reference pixel -> target pixel, Eq. 3): the warped target
+ * at (x, v) is the target read bilinearly (clamped) at H (x + delta_p, v, 1),
+ * and the shift back gives disp(u, v) = u - X with (X, Y) = H (u - l +
+ * delta_p, v, 1), the column of the correspondence in the target.  For rigs
+ * outside the rectified hypotheses of Sec. 3.1.  The plan must have
+ * perspective = 1; H must be finite with a positive third row over the
+ * reference columns [delta_p - D + 1, W - 1 + delta_p] x rows [0, H - 1]
+ * (checked at the corners).  H = NULL restores the plane's row shift.  Plans
+ * with a homography work with stereo_warp, stereo_match (plain and batched);
+ * the tracked and differentiable entry points reject them. */
+stereo_status stereo_plan_set_homography(stereo_plan_t plan, const double* H);
+
 /* ---- tuning knobs (host only) ---------------------------------------------
  * Launch-shape choices.  Keys:
  *   "agg_levels_u8", "agg_levels_f32": disparity levels staged per pass of

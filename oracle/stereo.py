@@ -70,6 +70,61 @@ def warp(tar, plane, delta_p, perspective=True):
     return lerp_row(t, v, X)
 
 
+def plane_homography(plane):
+    """The row shift of the plane as a homography (Eq. 3 under the
+    hypotheses of Sec. 3.1): H (u, v, 1) = (u - d_road(u, v), v, 1)."""
+    c0, c1, c2 = (float(c) for c in plane)
+    return np.array([[1.0 - c1, -c2, -c0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+
+
+def homography_map(Hm, u, v):
+    """Eq. (3): the target point (X, Y) of the reference point (u, v)."""
+    Hm = np.asarray(Hm, F64).reshape(3, 3)
+    u = np.asarray(u, F64)
+    v = np.asarray(v, F64)
+    x = Hm[0, 0] * u + Hm[0, 1] * v + Hm[0, 2]
+    y = Hm[1, 0] * u + Hm[1, 1] * v + Hm[1, 2]
+    z = Hm[2, 0] * u + Hm[2, 1] * v + Hm[2, 2]
+    return x / z, y / z
+
+
+def bilerp(img, X, Y):
+    """Bilinear interpolation at real (X, Y), each clamped to the image."""
+    H, W = img.shape
+    Xc = np.clip(np.asarray(X, F64), 0.0, W - 1.0)
+    Yc = np.clip(np.asarray(Y, F64), 0.0, H - 1.0)
+    i0 = np.floor(Xc).astype(np.int64)
+    j0 = np.floor(Yc).astype(np.int64)
+    fx = Xc - i0
+    fy = Yc - j0
+    i1 = np.minimum(i0 + 1, W - 1)
+    j1 = np.minimum(j0 + 1, H - 1)
+    top = (1.0 - fx) * img[j0, i0] + fx * img[j0, i1]
+    bot = (1.0 - fx) * img[j1, i0] + fx * img[j1, i1]
+    return (1.0 - fy) * top + fy * bot
+
+
+def warp_homography(tar, Hm, delta_p):
+    """Sec. 3.1 with the general homography of Eq. (3): the warped target at
+    (x, v) is the target at H (x + delta_p, v, 1)^T, read bilinearly with
+    clamped coordinates, so that a point of the road plane lands at level
+    delta_p.  For H = plane_homography(plane) this is warp()."""
+    t = np.asarray(tar, F64)
+    H, W = t.shape
+    v, x = np.mgrid[0:H, 0:W]
+    X, Y = homography_map(Hm, x + delta_p, v)
+    return bilerp(t, X, Y)
+
+
+def shift_back_homography(ell, valid, Hm, delta_p):
+    """Disparity along the row of the general warp: u - X where (X, Y) =
+    H (u - l + delta_p, v); the plane case gives shift_back().  NaN if invalid."""
+    H, W = ell.shape
+    v, u = np.mgrid[0:H, 0:W]
+    X, _ = homography_map(Hm, u - ell + delta_p, v)
+    return np.where(valid, u - X, np.nan)
+
+
 # --------------------------------------------------------------------------
 # Matching cost, Eq. (8)
 # --------------------------------------------------------------------------
@@ -230,7 +285,9 @@ def match(ref, tar, p, keep_volumes=False):
     bil_radius, sigma_s, sigma_r, lr_delta (e.g. a synth.Workload).
     """
     delta_p = p.delta_p if p.perspective else 0.0
-    tar_w = warp(tar, p.plane, delta_p, p.perspective)
+    Hm = getattr(p, "homography", None) if p.perspective else None
+    tar_w = warp(tar, p.plane, delta_p, p.perspective) if Hm is None \
+        else warp_homography(tar, Hm, delta_p)
     CR, CT = ncc_volumes(ref, tar_w, p.num_disp, p.ncc_radius)
     ER = bilateral(CR, ref, p.bil_radius, p.sigma_s, p.sigma_r)
     ET = bilateral(CT, tar_w, p.bil_radius, p.sigma_s, p.sigma_r)
@@ -238,7 +295,8 @@ def match(ref, tar, p, keep_volumes=False):
     dT = wta(ET)
     ell = subpixel(ER, dR)
     valid = lr_check(dR, dT, p.lr_delta)
-    disp = shift_back(ell, valid, p.plane, delta_p, p.perspective)
+    disp = shift_back(ell, valid, p.plane, delta_p, p.perspective) if Hm is None \
+        else shift_back_homography(ell, valid, Hm, delta_p)
     out = dict(tar_w=tar_w, dint_R=dR, dint_T=dT, ell=ell, valid=valid,
                disp=disp)
     if keep_volumes:
@@ -296,8 +354,10 @@ def aggregated_at(ref, tar_w, u, v, p, volume="R"):
 def match_at(ref, tar, p, pixels, tar_w=None):
     """Plain-path outputs at a list of (u, v) pixels (sampled full-size checks)."""
     delta_p = p.delta_p if p.perspective else 0.0
+    Hm = getattr(p, "homography", None) if p.perspective else None
     if tar_w is None:
-        tar_w = warp(tar, p.plane, delta_p, p.perspective)
+        tar_w = warp(tar, p.plane, delta_p, p.perspective) if Hm is None \
+            else warp_homography(tar, Hm, delta_p)
     H, W = np.shape(ref)
     D = p.num_disp
     out = []
@@ -315,7 +375,9 @@ def match_at(ref, tar, p, pixels, tar_w=None):
             valid = (dR - dT) ** 2 <= p.lr_delta
         else:
             dT, gapT, valid = -1, np.inf, False
-        if p.perspective:
+        if Hm is not None:
+            disp = u - float(homography_map(Hm, u - ell + delta_p, v)[0])
+        elif p.perspective:
             disp = ell - delta_p + float(d_road(p.plane, u - ell + delta_p, v))
         else:
             disp = ell

@@ -92,6 +92,7 @@ SIGNATURES = {
     "stereo_road_transform_tracked": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double,
                                               c_int32, c_float, c_void_p, c_void_p, c_void_p,
                                               c_void_p, c_size_t, c_void_p]),
+    "stereo_plan_set_homography": (c_int, [c_void_p, c_void_p]),
     "stereo_damage_mask": (c_int, [c_void_p, c_void_p, c_float, c_float, c_void_p, c_void_p]),
     "stereo_soft_forward": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_double), c_void_p,
                                     c_void_p, c_void_p, c_size_t, c_void_p]),

@@ -77,6 +77,7 @@ class Plan:
         check(lib.stereo_plan_create(ctypes.byref(params), ctypes.byref(h)))
         self._h = h
         self.params = params
+        self.homography = None
         n = ctypes.c_size_t()
         check(lib.stereo_plan_workspace_bytes(h, ctypes.byref(n)))
         self.workspace_bytes = int(n.value)
@@ -84,7 +85,10 @@ class Plan:
 
     @classmethod
     def from_workload(cls, w, **override):
-        return cls(params_from_workload(w, **override))
+        plan = cls(params_from_workload(w, **override))
+        if getattr(w, "homography", None) is not None and plan.params.perspective:
+            plan.set_homography(w.homography)
+        return plan
 
     @property
     def handle(self):
@@ -105,6 +109,19 @@ class Plan:
     @property
     def img_dtype(self):
         return torch.uint8 if self.params.dtype == _lib.U8 else torch.float32
+
+    def set_homography(self, H):
+        """Full Eq. (3) warp by the 3x3 homography H (None: the plane's row shift)."""
+        if H is None:
+            check(_lib.load().stereo_plan_set_homography(self.handle, None))
+            self.homography = None
+            return
+        vals = [float(x) for x in (H.ravel().tolist() if hasattr(H, "ravel") else list(H))]
+        if len(vals) != 9:
+            raise ValueError("H must have 9 entries")
+        arr = (ctypes.c_double * 9)(*vals)
+        check(_lib.load().stereo_plan_set_homography(self.handle, ctypes.cast(arr, ctypes.c_void_p)))
+        self.homography = tuple(vals)
 
     def set_tuning(self, key: str, value: int):
         lib = _lib.load()

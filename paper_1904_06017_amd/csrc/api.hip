@@ -181,6 +181,26 @@ stereo_status stereo_plan_workspace_bytes(stereo_plan_t plan, size_t* bytes) {
   return STEREO_OK;
 }
 
+stereo_status stereo_plan_set_homography(stereo_plan_t plan, const double* H) {
+  STEREO_REQUIRE(plan, "plan is NULL");
+  Plan& P = plan->P;
+  if (!H) {
+    P.homog = 0;
+    return STEREO_OK;
+  }
+  STEREO_REQUIRE(P.p.perspective == 1, "a homography needs a plan with perspective = 1");
+  for (int k = 0; k < 9; ++k) STEREO_REQUIRE(std::isfinite(H[k]), "H[%d] is not finite", k);
+  const double dp = (double)P.p.delta_p;
+  const double us[2] = {dp - P.D + 1, P.W - 1 + dp}, vs[2] = {0.0, (double)(P.H - 1)};
+  for (double u : us)
+    for (double v : vs)
+      STEREO_REQUIRE(H[6] * u + H[7] * v + H[8] > 0.0,
+                     "H maps (%g, %g) to or behind the plane at infinity", u, v);
+  for (int k = 0; k < 9; ++k) P.Hm[k] = H[k];
+  P.homog = 1;
+  return STEREO_OK;
+}
+
 stereo_status stereo_plan_set_tuning(stereo_plan_t plan, const char* key, int32_t value) {
   STEREO_REQUIRE(plan && key, "plan and key must be non-NULL");
   const std::string k(key);
@@ -389,6 +409,7 @@ stereo_status stereo_match_tracked(stereo_plan_t plan, const void* ref, const vo
                                    void* ws, size_t ws_bytes, hipStream_t stream) {
   STEREO_REQUIRE(plan && state_dev, "plan and state_dev must be non-NULL");
   STEREO_REQUIRE(plan->P.p.perspective == 1, "tracking needs a plan with perspective = 1");
+  STEREO_REQUIRE(!plan->P.homog, "tracking follows the plane model; the plan has a homography");
   return match_impl(plan, ref, tar, state_dev, dint_R, dint_T, dsub, valid, disp, ws, ws_bytes,
                     nullptr, stream);
 }

@@ -37,6 +37,8 @@ struct Plan {
   // tuning (stereo_plan_set_tuning): levels per aggregation pass by guide type
   int agg_levels_u8 = 8;
   int agg_levels_f32 = 8;
+  int homog = 0;        // 1: warp / shift back by the homography Hm (Eq. 3)
+  double Hm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   int ncc_levels = 0;   // levels per NCC workgroup (16, 32 or 64; DC / 4 waves);
                         // 0: 64 / 32 / 16 by the levels of the launch
   // differentiable form (F32 plans): levels recomputed per backward tile and
@@ -153,10 +155,15 @@ hipError_t launch_lr_check_tracked(const Plan& P, const int16_t* dR, const int16
 // blocks [first[j], first[j+1]) of the launch (first[0] = 0, first[n] = the
 // launch's block count) and runs exactly the per-pair kernel's code on its own
 // block grid, so a batched result is bitwise the per-pair one.
+struct Homog {              // row-major 3x3, by value in kernel arguments
+  double h[9];
+};
 struct WarpJob {            // grid: gx = ceil(W / 256) x H rows
   const void* tar; int64_t pitch; float* out;
   double dp, c0, c1, c2;
   int W, H, persp, gx;
+  int homog;                // 1: by Hm (Eq. 3) instead of the plane
+  Homog Hm;
 };
 struct StatsJob {           // grid: gx = ceil((W + 2r) / 64) x ceil(H / 16)
   const void* img; int64_t pitch; float* z; float* isd;
@@ -173,6 +180,8 @@ struct LrJob {              // grid: gx = ceil(W / 256) x H rows
   double dp, c0, c1, c2;
   float lr_delta;
   int W, H, use_lr, persp, gx;
+  int homog;
+  Homog Hm;
 };
 int warp_job_blocks(const Plan& P);
 int stats_job_blocks(int W, int H, int r);

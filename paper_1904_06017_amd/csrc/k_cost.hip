@@ -28,7 +28,10 @@ __device__ __forceinline__ void warp_body(const T* __restrict__ tar, int64_t pit
   if (!persp) {
     val = ld(row + x);
   } else {
-    const double X = (double)x + delta_p - (c0 + c1 * ((double)x + delta_p) + c2 * (double)v);
+    // explicit fused multiply-adds: the rounding does not depend on how the
+    // compiler contracts the expression where this body is inlined
+    const double ux = (double)x + delta_p;
+    const double X = ux - fma(c2, (double)v, fma(c1, ux, c0));
     int i0;
     float f;
     if (X <= 0.0) {
@@ -41,9 +44,42 @@ __device__ __forceinline__ void warp_body(const T* __restrict__ tar, int64_t pit
       f = (float)(X - fl);
     }
     const int i1 = min(i0 + 1, W - 1);
-    val = (1.0f - f) * ld(row + i0) + f * ld(row + i1);
+    val = fmaf(f, ld(row + i1), (1.0f - f) * ld(row + i0));
   }
   out[(int64_t)v * W + x] = val;
+}
+
+// Eq. (3) in full: tar_w(x, v) = target at H (x + delta_p, v, 1)^T, read
+// bilinearly with both coordinates clamped; positions in FP64.
+template <typename T>
+__device__ __forceinline__ void warp_h_body(const T* __restrict__ tar, int64_t pitch, int W,
+                                            int H, double delta_p, const Homog& M,
+                                            float* __restrict__ out, int bx, int v) {
+  const int x = bx * 256 + threadIdx.x;
+  if (x >= W) return;
+  const double* h = M.h;
+  const double u = (double)x + delta_p, vv = (double)v;
+  const double z = fma(h[6], u, fma(h[7], vv, h[8]));
+  double X = fma(h[0], u, fma(h[1], vv, h[2])) / z;
+  double Y = fma(h[3], u, fma(h[4], vv, h[5])) / z;
+  X = fmin(fmax(X, 0.0), (double)(W - 1));
+  Y = fmin(fmax(Y, 0.0), (double)(H - 1));
+  const double fx0 = floor(X), fy0 = floor(Y);
+  const int i0 = (int)fx0, j0 = (int)fy0;
+  const int i1 = min(i0 + 1, W - 1), j1 = min(j0 + 1, H - 1);
+  const float fx = (float)(X - fx0), fy = (float)(Y - fy0);
+  const T* r0 = tar + (int64_t)j0 * pitch;
+  const T* r1 = tar + (int64_t)j1 * pitch;
+  const float top = fmaf(fx, ld(r0 + i1), (1.0f - fx) * ld(r0 + i0));
+  const float bot = fmaf(fx, ld(r1 + i1), (1.0f - fx) * ld(r1 + i0));
+  out[(int64_t)v * W + x] = fmaf(fy, bot, (1.0f - fy) * top);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+warp_h_kernel(const T* __restrict__ tar, int64_t pitch, int W, int H, double delta_p, Homog M,
+              float* __restrict__ out) {
+  warp_h_body<T>(tar, pitch, W, H, delta_p, M, out, blockIdx.x, blockIdx.y);
 }
 
 template <typename T>
@@ -283,8 +319,12 @@ warp_jobs_kernel(const WarpJob* __restrict__ jobs, const int* __restrict__ first
   const int j = job_of(first, n, blockIdx.x);
   const WarpJob& J = jobs[j];
   const int l = blockIdx.x - first[j];
-  warp_body<T>(static_cast<const T*>(J.tar), J.pitch, J.W, J.dp, J.c0, J.c1, J.c2, J.persp,
-               J.out, l % J.gx, l / J.gx);
+  if (J.homog)
+    warp_h_body<T>(static_cast<const T*>(J.tar), J.pitch, J.W, J.H, J.dp, J.Hm, J.out,
+                   l % J.gx, l / J.gx);
+  else
+    warp_body<T>(static_cast<const T*>(J.tar), J.pitch, J.W, J.dp, J.c0, J.c1, J.c2, J.persp,
+                 J.out, l % J.gx, l / J.gx);
 }
 
 template <typename T>
@@ -389,6 +429,8 @@ WarpJob warp_job(const Plan& P, const void* tar, float* tar_w) {
   J.dp = p.perspective ? (double)p.delta_p : 0.0;
   J.c0 = p.plane[0]; J.c1 = p.plane[1]; J.c2 = p.plane[2];
   J.W = P.W; J.H = P.H; J.persp = p.perspective; J.gx = (P.W + 255) / 256;
+  J.homog = P.homog;
+  for (int k = 0; k < 9; ++k) J.Hm.h[k] = P.Hm[k];
   return J;
 }
 
@@ -473,6 +515,17 @@ hipError_t launch_ncc_jobs(int r, stereo_dtype dt, int quad, const NccJob* jobs,
 hipError_t launch_warp(const Plan& P, const void* tar, float* tar_w, hipStream_t s) {
   dim3 grid((P.W + 255) / 256, P.H);
   const stereo_params& p = P.p;
+  if (P.homog) {
+    Homog M;
+    for (int k = 0; k < 9; ++k) M.h[k] = P.Hm[k];
+    if (p.dtype == STEREO_U8)
+      hipLaunchKernelGGL(warp_h_kernel<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)tar,
+                         p.pitch_tar, P.W, P.H, (double)p.delta_p, M, tar_w);
+    else
+      hipLaunchKernelGGL(warp_h_kernel<float>, grid, dim3(256), 0, s, (const float*)tar,
+                         p.pitch_tar, P.W, P.H, (double)p.delta_p, M, tar_w);
+    return hipGetLastError();
+  }
   const double dp = p.perspective ? (double)p.delta_p : 0.0;
   if (p.dtype == STEREO_U8)
     hipLaunchKernelGGL(warp_kernel<uint8_t>, grid, dim3(256), 0, s,

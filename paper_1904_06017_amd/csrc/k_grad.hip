@@ -328,7 +328,8 @@ warp_adjoint_kernel(const T* __restrict__ tar, int64_t pitch, const float* __res
   const int x = blockIdx.x * kT + threadIdx.x, v = blockIdx.y;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   if (x < W) {
-    const double X = (double)x + dp - (c0 + c1 * ((double)x + dp) + c2 * (double)v);
+    const double ux = (double)x + dp;             // as the forward warp
+    const double X = ux - fma(c2, (double)v, fma(c1, ux, c0));
     int i0;
     double f;
     bool inside = false;
@@ -515,6 +516,7 @@ T* at(void* ws, size_t off) {
 stereo_status check_grad(const Plan& P, void* ws, size_t bytes) {
   REQ(P.p.dtype == STEREO_F32, "the differentiable form needs an F32 plan");
   REQ(P.p.perspective == 1, "the differentiable form needs perspective = 1");
+  REQ(!P.homog, "the differentiable form differentiates the plane, not a homography");
   REQ(ws != nullptr, "workspace is NULL");
   if (bytes < P.ws_bytes)
     return fail(STEREO_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < required %zu", bytes,

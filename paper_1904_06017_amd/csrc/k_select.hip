@@ -56,9 +56,44 @@ __device__ __forceinline__ void lr_body(const int16_t* __restrict__ dR,
   if (disp) {
     const double ell = dsub ? (double)dsub[p] : (double)d;
     double out = ell;
-    if (persp) out = ell - delta_p + (c0 + c1 * ((double)u - ell + delta_p) + c2 * (double)v);
+    if (persp) out = ell - delta_p + fma(c2, (double)v, fma(c1, (double)u - ell + delta_p, c0));
     disp[p] = ok ? (float)out : __builtin_nanf("");
   }
+}
+
+// The same check; the shift back by the homography: disp = u - X with
+// (X, Y) = H (u - l + delta_p, v, 1) (Eq. 3), in FP64.
+__device__ __forceinline__ void lr_h_body(const int16_t* __restrict__ dR,
+                                          const int16_t* __restrict__ dT,
+                                          const float* __restrict__ dsub, int W, float lr_delta,
+                                          int use_lr, double delta_p, const Homog& M,
+                                          uint8_t* __restrict__ valid, float* __restrict__ disp,
+                                          int bx, int v) {
+  const int u = bx * 256 + threadIdx.x;
+  if (u >= W) return;
+  const int64_t p = (int64_t)v * W + u;
+  const int d = dR[p];
+  const int x = u - d;
+  bool ok = x >= 0;
+  if (ok && use_lr) {
+    const float diff = (float)(d - (int)dT[(int64_t)v * W + x]);
+    ok = diff * diff <= lr_delta;
+  }
+  if (valid) valid[p] = ok ? 1 : 0;
+  if (disp) {
+    const double ell = dsub ? (double)dsub[p] : (double)d;
+    const double* h = M.h;
+    const double uu = (double)u - ell + delta_p, vv = (double)v;
+    const double X = fma(h[0], uu, fma(h[1], vv, h[2])) / fma(h[6], uu, fma(h[7], vv, h[8]));
+    disp[p] = ok ? (float)((double)u - X) : __builtin_nanf("");
+  }
+}
+
+__global__ void __launch_bounds__(256)
+lr_h_kernel(const int16_t* __restrict__ dR, const int16_t* __restrict__ dT,
+            const float* __restrict__ dsub, int W, float lr_delta, int use_lr, double delta_p,
+            Homog M, uint8_t* __restrict__ valid, float* __restrict__ disp) {
+  lr_h_body(dR, dT, dsub, W, lr_delta, use_lr, delta_p, M, valid, disp, blockIdx.x, blockIdx.y);
 }
 
 __global__ void __launch_bounds__(256)
@@ -93,8 +128,12 @@ lr_jobs_kernel(const LrJob* __restrict__ jobs, const int* __restrict__ first, in
   const int j = job_of(first, n, blockIdx.x);
   const LrJob& J = jobs[j];
   const int l = blockIdx.x - first[j];
-  lr_body(J.dR, J.dT, J.dsub, J.W, J.lr_delta, J.use_lr, J.persp, J.dp, J.c0, J.c1, J.c2,
-          J.valid, J.disp, l % J.gx, l / J.gx);
+  if (J.homog)
+    lr_h_body(J.dR, J.dT, J.dsub, J.W, J.lr_delta, J.use_lr, J.dp, J.Hm, J.valid, J.disp,
+              l % J.gx, l / J.gx);
+  else
+    lr_body(J.dR, J.dT, J.dsub, J.W, J.lr_delta, J.use_lr, J.persp, J.dp, J.c0, J.c1, J.c2,
+            J.valid, J.disp, l % J.gx, l / J.gx);
 }
 
 }  // namespace
@@ -119,6 +158,8 @@ LrJob lr_job(const Plan& P, const int16_t* dR, const int16_t* dT, const float* d
   J.lr_delta = p.lr_delta;
   J.W = P.W; J.H = P.H; J.use_lr = (p.lr_check && dT) ? 1 : 0; J.persp = p.perspective;
   J.gx = (P.W + 255) / 256;
+  J.homog = P.homog;
+  for (int k = 0; k < 9; ++k) J.Hm.h[k] = P.Hm[k];
   return J;
 }
 
@@ -143,6 +184,14 @@ hipError_t launch_lr_check(const Plan& P, const int16_t* dR, const int16_t* dT,
                            const float* dsub, uint8_t* valid, float* disp,
                            hipStream_t s) {
   const stereo_params& p = P.p;
+  if (P.homog) {
+    Homog M;
+    for (int k = 0; k < 9; ++k) M.h[k] = P.Hm[k];
+    hipLaunchKernelGGL(lr_h_kernel, dim3((P.W + 255) / 256, P.H), dim3(256), 0, s, dR, dT,
+                       dsub, P.W, p.lr_delta, (p.lr_check && dT) ? 1 : 0, (double)p.delta_p,
+                       M, valid, disp);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(lr_kernel, dim3((P.W + 255) / 256, P.H), dim3(256), 0, s, dR, dT,
                      dsub, P.W, P.H, p.lr_delta, (p.lr_check && dT) ? 1 : 0,
                      p.perspective, p.perspective ? (double)p.delta_p : 0.0,

@@ -7,7 +7,8 @@ any computation.
 """
 from .presets import (Workload, WORKLOADS, workload, batch_workloads,
                       crop_workload)
-from .scenes import Scene, make_scene, make_workload_pair, road_sequence
+from .scenes import (Scene, make_scene, make_workload_pair, road_sequence, skew_matrix,
+                     skewed_pair)
 
-__all__ = ["road_sequence", "Workload", "WORKLOADS", "workload", "batch_workloads",
+__all__ = ["skew_matrix", "skewed_pair", "road_sequence", "Workload", "WORKLOADS", "workload", "batch_workloads",
            "crop_workload", "Scene", "make_scene", "make_workload_pair"]

@@ -43,6 +43,8 @@ class Workload:
     lr_delta: float = 1.0      # delta_r of Eq. (12)
     lr_check: bool = True
     softargmin_T: float = 0.1
+    # full Eq. (3) warp in place of the plane's row shift: 9 entries, row-major
+    homography: Tuple[float, ...] = None
 
     @property
     def true_plane(self):

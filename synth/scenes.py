@@ -188,3 +188,45 @@ def road_sequence(width, height, n_frames, seed, n_potholes=4, n_cracks=1, slope
         out.append((c, psi, make_scene(width, height, c, n_potholes, n_cracks, s,
                                        float_images=float_images)))
     return out
+
+
+def skew_matrix(width, height, angle_deg=0.3, dy=0.8):
+    """A small in-plane rotation of the target camera about the image centre
+    plus a vertical offset: a rig outside the rectified hypotheses."""
+    a = math.radians(angle_deg)
+    cx, cy = (width - 1) / 2.0, (height - 1) / 2.0
+    c, s = math.cos(a), math.sin(a)
+    return np.array([[c, -s, cx - c * cx + s * cy],
+                     [s, c, cy - s * cx - c * cy + dy],
+                     [0.0, 0.0, 1.0]])
+
+
+def skewed_pair(w: Workload, angle_deg=0.3, dy=0.8):
+    """The workload's pair with the target re-imaged by skew_matrix G:
+    tar2(p) = tar(G^-1 p) (bilinear, clamped; rounded for uint8).  Returns
+    (scene, tar2, G, H, disp_true) where H = G . (row shift of the true plane)
+    maps reference pixels of the road plane into tar2, and disp_true(u, v) is
+    u minus the column of the true correspondence in tar2."""
+    sc = make_workload_pair(w)
+    H_, W_ = sc.tar.shape
+    G = skew_matrix(W_, H_, angle_deg, dy)
+    Gi = np.linalg.inv(G)
+    vv, uu = np.mgrid[0:H_, 0:W_].astype(np.float64)
+    den = Gi[2, 0] * uu + Gi[2, 1] * vv + Gi[2, 2]
+    X = (Gi[0, 0] * uu + Gi[0, 1] * vv + Gi[0, 2]) / den
+    Y = (Gi[1, 0] * uu + Gi[1, 1] * vv + Gi[1, 2]) / den
+    t = sc.tar.astype(np.float64)
+    Xc, Yc = np.clip(X, 0, W_ - 1.0), np.clip(Y, 0, H_ - 1.0)
+    i0, j0 = np.floor(Xc).astype(np.int64), np.floor(Yc).astype(np.int64)
+    i1, j1 = np.minimum(i0 + 1, W_ - 1), np.minimum(j0 + 1, H_ - 1)
+    fx, fy = Xc - i0, Yc - j0
+    t2 = ((1 - fy) * ((1 - fx) * t[j0, i0] + fx * t[j0, i1]) +
+          fy * ((1 - fx) * t[j1, i0] + fx * t[j1, i1]))
+    tar2 = (t2.astype(np.float32) if w.dtype == "f32"
+            else np.clip(np.rint(t2), 0, 255).astype(np.uint8))
+    c0, c1, c2 = w.true_plane
+    Hrow = np.array([[1.0 - c1, -c2, -c0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    H = G @ Hrow
+    xt = uu - sc.d_gt                      # true correspondence in the rectified target
+    xs = (G[0, 0] * xt + G[0, 1] * vv + G[0, 2]) / (G[2, 0] * xt + G[2, 1] * vv + G[2, 2])
+    return sc, tar2, G, H, uu - xs

@@ -148,3 +148,20 @@ def test_damage_mask_argument_checks(lib):
     assert lib.stereo_damage_mask(h, buf, ctypes.c_float(0.0), ctypes.c_float(float("nan")),
                                   buf, None) == 1
     lib.stereo_plan_destroy(h)
+
+
+def test_homography_argument_checks(lib):
+    p = make_params(64, 48, 16, delta_p=8, plane=(4, 0, 0.1))
+    s, h = _create(lib, p)
+    H = (ctypes.c_double * 9)(1, 0, -4, 0, 1, 0, 0, 0, 1)
+    assert lib.stereo_plan_set_homography(h, H) == 0
+    assert lib.stereo_plan_set_homography(h, None) == 0          # back to the row shift
+    bad = (ctypes.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, float("nan"))
+    assert lib.stereo_plan_set_homography(h, bad) == 1
+    behind = (ctypes.c_double * 9)(1, 0, 0, 0, 1, 0, -0.1, 0, 1)  # z <= 0 at the far columns
+    assert lib.stereo_plan_set_homography(h, behind) == 1
+    lib.stereo_plan_destroy(h)
+    raw = make_params(64, 48, 16, perspective=False)
+    s, h = _create(lib, raw)
+    assert lib.stereo_plan_set_homography(h, H) == 1              # needs perspective = 1
+    lib.stereo_plan_destroy(h)

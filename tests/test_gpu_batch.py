@@ -141,3 +141,22 @@ def test_batch_autotune(small_batch, tmp_path):
     for e, g in zip(ref, got):
         for k in e:
             assert np.array_equal(e[k], g[k], equal_nan=True)
+
+
+def test_batch_with_homography_pair(small_batch):
+    """A pair warped by a general homography (Eq. 3) next to plane pairs:
+    every pair is bitwise its per-pair result."""
+    from dataclasses import replace
+    from synth import crop_workload, skewed_pair, workload
+    w = crop_workload(workload("c1"), 170, 90, num_disp=36, delta_p=18.0)
+    sc, tar2, _, Hm, _ = skewed_pair(w, angle_deg=0.4, dy=0.7)
+    wh = replace(w, homography=tuple(Hm.ravel()))
+    items = _make(small_batch[:2])
+    items.insert(1, (api.Plan.from_workload(wh), torch.from_numpy(sc.ref).cuda(),
+                     torch.from_numpy(tar2).cuda()))
+    b = api.Batch(items)
+    outs = [{k: _host(v) for k, v in o.items()} for o in b.submit()]
+    for (plan, ref, tar), o in zip(items, outs):
+        m = api.match(plan, ref, tar)
+        for k in ("dint_R", "valid", "disp"):
+            assert np.array_equal(_host(m[k]), o[k], equal_nan=True), k

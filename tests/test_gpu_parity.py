@@ -14,7 +14,7 @@ import torch
 
 import oracle.road as ORD
 import oracle.stereo as OS
-from synth import crop_workload, make_scene, make_workload_pair, workload
+from synth import crop_workload, make_scene, make_workload_pair, skewed_pair, workload
 from tests import parity_rules as PR
 
 pytestmark = pytest.mark.gpu
@@ -65,7 +65,16 @@ def _f32():
     return w, make_scene(w.width, w.height, w.plane, 2, 1, 24, float_images=True)
 
 
-CASES = {"c1": _c1, "c2_ragged": _c2_ragged, "rolled": _rolled, "raw": _raw, "f32": _f32}
+def _skewed():
+    """A rig outside the rectified hypotheses: the target camera rotated by
+    0.4 degrees and shifted 0.7 rows; matched through the full Eq. (3) warp."""
+    w = crop_workload(workload("c1"), 170, 90, num_disp=36, delta_p=18.0)
+    sc, tar2, _, Hm, _ = skewed_pair(w, angle_deg=0.4, dy=0.7)
+    return replace(w, homography=tuple(Hm.ravel())), replace(sc, tar=tar2)
+
+
+CASES = {"c1": _c1, "c2_ragged": _c2_ragged, "rolled": _rolled, "raw": _raw, "f32": _f32,
+         "skewed": _skewed}
 _cache = {}
 
 
