@@ -154,21 +154,11 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
     m2[k] = -3.402823466e38f; Zs[k] = 0.0f; S1[k] = 0.0f;
   }
   const float zscale = -o.invT * 1.4426950408889634f;
-  // modes 5, 6: per-pixel state of the softmax adjoint and the two running sums
-  float sbase[PX2], sgp[PX2], sdh[PX2], sa[PX2], sb[PX2];
+  // modes 5, 6: the two running sums per pixel (the softmax state of mode 5
+  // is re-read in each pass's epilogue rather than held in registers)
+  float sa[PX2], sb[PX2];
 #pragma unroll
-  for (int k = 0; k < PX2; ++k) {
-    sbase[k] = 0.0f; sgp[k] = 0.0f; sdh[k] = 0.0f; sa[k] = 0.0f; sb[k] = 0.0f;
-    if (MODE == 5) {
-      const int px = x0 + tx * PX + k, py = y0 + ty;
-      if (py < H && px < W) {
-        const int64_t pix = (int64_t)py * W + px;
-        sbase[k] = -(o.sm_m[pix] + o.sm_logZ[pix]);
-        sgp[k] = o.gD[pix] * o.one_minus_c1 * (-o.invT);
-        sdh[k] = o.sm_dh[pix];
-      }
-    }
-  }
+  for (int k = 0; k < PX2; ++k) { sa[k] = 0.0f; sb[k] = 0.0f; }
 
   // element step from level d to d + 1 (the target volume also moves one
   // column to the right per level)
@@ -330,14 +320,21 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
       } else if constexpr (MODE == 5) {
         // softmax adjoint: P = exp(-E/T - m - log Z), dE = g' (-1/T) P (d - dh)
         const bool in = py < H && px < W;
+        float sbase = 0.0f, sgp = 0.0f, sdh = 0.0f;
+        if (in) {
+          const int64_t pix = (int64_t)py * W + px;
+          sbase = -(o.sm_m[pix] + o.sm_logZ[pix]);
+          sgp = o.gD[pix] * o.one_minus_c1 * (-o.invT);
+          sdh = o.sm_dh[pix];
+        }
 #pragma unroll
         for (int j = 0; j < DC; ++j) {
           const int d = d0 + j;
           if (d < D) {
             const float e = acc[k][j] * rinv[k];
-            const float P = __builtin_amdgcn_exp2f(fmaf(-e, o.invT, sbase[k]) *
+            const float P = __builtin_amdgcn_exp2f(fmaf(-e, o.invT, sbase) *
                                                    1.4426950408889634f);
-            const float dE = sgp[k] * P * ((float)(o.d_first + d) - sdh[k]);
+            const float dE = sgp * P * ((float)(o.d_first + d) - sdh);
             if (in) o.E[((int64_t)d * H + py) * W + px] = dE * rinv[k];
             sa[k] = fmaf(dE, e, sa[k]);
             sb[k] = fmaf(dE, acc2[k][j], sb[k]);
@@ -453,8 +450,10 @@ __device__ __forceinline__ void bilateral_tile(const BilPair& a, int x0, int y0,
   }
 }
 
+// Two workgroups per CU at 8 levels per pass (16 waves, 4 per SIMD): at most
+// 128 VGPRs; at 16 levels the LDS allows one.
 template <int R, int PX, int DC, int TYT, typename GT, int MODE>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, DC == 8 ? 4 : 2)
 bilateral_kernel(BilPair a) {
   extern __shared__ float4 lds4[];
   using Gm = BilGeom<R, PX, DC, TYT>;
