@@ -40,6 +40,8 @@ CASES = {
     # ragged sizes: several 32x32 / 16x16 tiles plus tails; D not a multiple of 16
     "c5_crop": dict(w=(150, 77), D=45, dp=22.0, plane=(24.0, 0.0, 0.1), R=5, r=3, seed=51),
     "rolled": dict(w=(130, 70), D=28, dp=14.0, plane=(14.3, -0.02, 0.09), R=4, r=2, seed=52),
+    # the compiled maximum radii
+    "max_radii": dict(w=(80, 40), D=20, dp=10.0, plane=(14.0, 0.01, 0.09), R=8, r=8, seed=55),
 }
 _cache = {}
 

@@ -73,8 +73,43 @@ def _skewed():
     return replace(w, homography=tuple(Hm.ravel())), replace(sc, tar=tar2)
 
 
+def _max_radii():
+    """The compiled maximum radii r = R = 8 (17x17 blocks and windows)."""
+    w = crop_workload(workload("c1"), 150, 60, num_disp=64, delta_p=32.0, ncc_radius=8,
+                      bil_radius=8, sigma_s=6.0, sigma_r=14.0)
+    return w, make_scene(w.width, w.height, w.plane, 1, 0, 41)
+
+
+def _d256():
+    """The largest disparity range, D = 256 (wider than most of the image)."""
+    w = crop_workload(workload("c1"), 300, 20, num_disp=256, delta_p=128.0, ncc_radius=1,
+                      bil_radius=1)
+    return w, make_scene(w.width, w.height, w.plane, 1, 0, 42)
+
+
+def _minimal():
+    """The smallest range D = 3 and radii 1 on an image narrower than two
+    tiles and shorter than one."""
+    w = crop_workload(workload("c1"), 37, 19, num_disp=3, delta_p=1.0, ncc_radius=1,
+                      bil_radius=1)
+    return w, make_scene(w.width, w.height, w.plane, 0, 0, 43)
+
+
+def _tiny():
+    """A 5x3 image: blocks and windows wider than the image."""
+    w = crop_workload(workload("c1"), 5, 3, num_disp=4, delta_p=2.0, ncc_radius=2,
+                      bil_radius=2)
+    return w, make_scene(w.width, w.height, w.plane, 0, 0, 44)
+
+
+def _one_row():
+    w = crop_workload(workload("c1"), 64, 1, num_disp=8, delta_p=4.0)
+    return w, make_scene(w.width, w.height, w.plane, 0, 0, 45)
+
+
 CASES = {"c1": _c1, "c2_ragged": _c2_ragged, "rolled": _rolled, "raw": _raw, "f32": _f32,
-         "skewed": _skewed}
+         "skewed": _skewed, "max_radii": _max_radii, "d256": _d256, "minimal": _minimal,
+         "tiny": _tiny, "one_row": _one_row}
 _cache = {}
 
 
