@@ -34,6 +34,7 @@ struct JobList {
   JobKind kind;
   stereo_dtype dt;
   int r;                      // NCC radius; statistics: largest radius
+  int dc = 16;                // NCC: levels per workgroup
   std::vector<int> pair;
   std::vector<int> which;     // statistics: 0 = reference, 1 = warped target
   std::vector<int> first;     // block prefix, size jobs + 1
@@ -155,9 +156,20 @@ void build_layout(stereo_batch_s& b) {
     push(Lt, i, 1, stats_job_blocks(P.W, P.H, P.r));
     Lt.r = std::max(Lt.r, P.r);
   }
+  // NCC: the largest level block every pair of the list fills, then the blocks
   for (int i = 0; i < n; ++i) {
     const Plan& P = b.plans[i];
-    push(list_of(JK_NCC, P.p.dtype, P.r), i, 0, ncc_job_blocks(P, P.W + P.D - 1, 0, P.D));
+    JobList& L = list_of(JK_NCC, P.p.dtype, P.r);
+    const int dc = P.D >= 64 ? 64 : P.D >= 32 ? 32 : 16;
+    L.dc = L.pair.empty() ? dc : std::min(L.dc, dc);
+    push(L, i, 0, 0);
+  }
+  for (JobList& L : b.lists) {
+    if (L.kind != JK_NCC) continue;
+    for (size_t k = 0; k < L.pair.size(); ++k) {
+      const Plan& P = b.plans[L.pair[k]];
+      L.first[k + 1] = L.first[k] + ncc_job_blocks(P, P.W + P.D - 1, 0, P.D, L.dc);
+    }
   }
   for (int i = 0; i < n; ++i)
     if (b.items[i].valid || b.items[i].disp)
@@ -277,7 +289,7 @@ stereo_status enqueue(stereo_batch_s& b, hipStream_t s) {
                                s), "batch statistics");
         break;
       case JK_NCC:
-        BHIP(launch_ncc_jobs(L.r, L.dt, 1, static_cast<const NccJob*>(jobs), first, nj, blocks,
+        BHIP(launch_ncc_jobs(L.r, L.dt, 1, L.dc, static_cast<const NccJob*>(jobs), first, nj, blocks,
                              s), "batch ncc");
         break;
       case JK_LR:

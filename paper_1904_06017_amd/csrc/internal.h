@@ -185,7 +185,7 @@ struct LrJob {              // grid: gx = ceil(W / 256) x H rows
 };
 int warp_job_blocks(const Plan& P);
 int stats_job_blocks(int W, int H, int r);
-int ncc_job_blocks(const Plan& P, int out_w, int d_first, int d_end);
+int ncc_job_blocks(const Plan& P, int out_w, int d_first, int d_end, int dc);
 int lr_job_blocks(const Plan& P);
 WarpJob warp_job(const Plan& P, const void* tar, float* tar_w);
 StatsJob stats_job(const Plan& P, const void* img, int64_t pitch, float* z, float* isd);
@@ -200,7 +200,8 @@ hipError_t launch_warp_jobs(stereo_dtype dt, const WarpJob* jobs, const int* fir
                             int blocks, hipStream_t s);
 hipError_t launch_stats_jobs(stereo_dtype dt, const StatsJob* jobs, const int* first, int n,
                              int blocks, int max_r, hipStream_t s);
-hipError_t launch_ncc_jobs(int r, stereo_dtype dt, int quad, const NccJob* jobs,
+// dc: levels per workgroup (16, 32 or 64), the same for every job of the list
+hipError_t launch_ncc_jobs(int r, stereo_dtype dt, int quad, int dc, const NccJob* jobs,
                            const int* first, int n, int blocks, hipStream_t s);
 hipError_t launch_lr_jobs(const LrJob* jobs, const int* first, int n, int blocks,
                           hipStream_t s);

@@ -338,8 +338,8 @@ stats_jobs_kernel(const StatsJob* __restrict__ jobs, const int* __restrict__ fir
                       l % J.gx, l / J.gx);
 }
 
-template <int r, typename T, int QUAD>
-__global__ void __launch_bounds__(256)
+template <int r, typename T, int QUAD, int DC>
+__global__ void __launch_bounds__(16 * DC)
 ncc_jobs_kernel(const NccJob* __restrict__ jobs, const int* __restrict__ first, int n) {
   extern __shared__ float sm[];
   const int j = job_of(first, n, blockIdx.x);
@@ -347,7 +347,7 @@ ncc_jobs_kernel(const NccJob* __restrict__ jobs, const int* __restrict__ first, 
   const int l = blockIdx.x - first[j];
   const int gxy = J.gx * J.gy;
   const int bz = l / gxy, rem = l - bz * gxy;
-  ncc_body<r, T, QUAD, NC_DC>(static_cast<const T*>(J.ref), J.ref_pitch, J.tarw, J.W, J.H, J.d_first,
+  ncc_body<r, T, QUAD, DC>(static_cast<const T*>(J.ref), J.ref_pitch, J.tarw, J.W, J.H, J.d_first,
                        J.d_end, J.zX, J.isdX, J.zY, J.isdY, J.C, J.out_w, J.out_pitch,
                        J.out_slice, J.anchor, sm, rem % J.gx, rem / J.gx, bz);
 }
@@ -417,9 +417,9 @@ int warp_job_blocks(const Plan& P) { return ((P.W + 255) / 256) * P.H; }
 int stats_job_blocks(int W, int H, int r) {
   return ((W + 2 * r + ST_TX - 1) / ST_TX) * ((H + ST_TY - 1) / ST_TY);
 }
-int ncc_job_blocks(const Plan& P, int out_w, int d_first, int d_end) {
+int ncc_job_blocks(const Plan& P, int out_w, int d_first, int d_end, int dc) {
   return ((out_w + NC_TX - 1) / NC_TX) * ((P.H + NC_TY - 1) / NC_TY) *
-         ((d_end - d_first + NC_DC - 1) / NC_DC);
+         ((d_end - d_first + dc - 1) / dc);
 }
 
 WarpJob warp_job(const Plan& P, const void* tar, float* tar_w) {
@@ -477,39 +477,48 @@ hipError_t launch_stats_jobs(stereo_dtype dt, const StatsJob* jobs, const int* f
 }
 
 namespace {
-template <int r, typename T>
-hipError_t ncc_jobs_r(int quad, const NccJob* jobs, const int* first, int n, int blocks,
-                      hipStream_t s) {
+template <int r, typename T, int DC>
+hipError_t ncc_jobs_rdc(int quad, const NccJob* jobs, const int* first, int n, int blocks,
+                        hipStream_t s) {
   if (quad)
-    hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 1>), dim3(blocks), dim3(16 * NC_DC),
-                       NccGeom<r>::lds_bytes, s, jobs, first, n);
+    hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 1, DC>), dim3(blocks), dim3(16 * DC),
+                       (NccGeom<r, DC>::lds_bytes), s, jobs, first, n);
   else
-    hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 0>), dim3(blocks), dim3(16 * NC_DC),
-                       NccGeom<r>::lds_bytes, s, jobs, first, n);
+    hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 0, DC>), dim3(blocks), dim3(16 * DC),
+                       (NccGeom<r, DC>::lds_bytes), s, jobs, first, n);
   return hipGetLastError();
 }
-template <typename T>
-hipError_t ncc_jobs_t(int r, int quad, const NccJob* jobs, const int* first, int n, int blocks,
+template <int r, typename T>
+hipError_t ncc_jobs_r(int quad, int dc, const NccJob* jobs, const int* first, int n, int blocks,
                       hipStream_t s) {
+  switch (dc) {
+    case 64: return ncc_jobs_rdc<r, T, 64>(quad, jobs, first, n, blocks, s);
+    case 32: return ncc_jobs_rdc<r, T, 32>(quad, jobs, first, n, blocks, s);
+    default: return ncc_jobs_rdc<r, T, 16>(quad, jobs, first, n, blocks, s);
+  }
+}
+template <typename T>
+hipError_t ncc_jobs_t(int r, int quad, int dc, const NccJob* jobs, const int* first, int n,
+                      int blocks, hipStream_t s) {
   switch (r) {
-    case 1: return ncc_jobs_r<1, T>(quad, jobs, first, n, blocks, s);
-    case 2: return ncc_jobs_r<2, T>(quad, jobs, first, n, blocks, s);
-    case 3: return ncc_jobs_r<3, T>(quad, jobs, first, n, blocks, s);
-    case 4: return ncc_jobs_r<4, T>(quad, jobs, first, n, blocks, s);
-    case 5: return ncc_jobs_r<5, T>(quad, jobs, first, n, blocks, s);
-    case 6: return ncc_jobs_r<6, T>(quad, jobs, first, n, blocks, s);
-    case 7: return ncc_jobs_r<7, T>(quad, jobs, first, n, blocks, s);
-    case 8: return ncc_jobs_r<8, T>(quad, jobs, first, n, blocks, s);
+    case 1: return ncc_jobs_r<1, T>(quad, dc, jobs, first, n, blocks, s);
+    case 2: return ncc_jobs_r<2, T>(quad, dc, jobs, first, n, blocks, s);
+    case 3: return ncc_jobs_r<3, T>(quad, dc, jobs, first, n, blocks, s);
+    case 4: return ncc_jobs_r<4, T>(quad, dc, jobs, first, n, blocks, s);
+    case 5: return ncc_jobs_r<5, T>(quad, dc, jobs, first, n, blocks, s);
+    case 6: return ncc_jobs_r<6, T>(quad, dc, jobs, first, n, blocks, s);
+    case 7: return ncc_jobs_r<7, T>(quad, dc, jobs, first, n, blocks, s);
+    case 8: return ncc_jobs_r<8, T>(quad, dc, jobs, first, n, blocks, s);
     default: return hipErrorInvalidValue;
   }
 }
 }  // namespace
 
-hipError_t launch_ncc_jobs(int r, stereo_dtype dt, int quad, const NccJob* jobs,
+hipError_t launch_ncc_jobs(int r, stereo_dtype dt, int quad, int dc, const NccJob* jobs,
                            const int* first, int n, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  if (dt == STEREO_U8) return ncc_jobs_t<uint8_t>(r, quad, jobs, first, n, blocks, s);
-  return ncc_jobs_t<float>(r, quad, jobs, first, n, blocks, s);
+  if (dt == STEREO_U8) return ncc_jobs_t<uint8_t>(r, quad, dc, jobs, first, n, blocks, s);
+  return ncc_jobs_t<float>(r, quad, dc, jobs, first, n, blocks, s);
 }
 
 hipError_t launch_warp(const Plan& P, const void* tar, float* tar_w, hipStream_t s) {
