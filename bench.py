@@ -327,6 +327,20 @@ def run(args):
                frac=round(ncc_bytes / (st["ncc_ms"] / 1e3) / 1e9 / MI355X_HBM_GBS, 4),
                bytes_per_launch=ncc_bytes)
 
+    # cost + filter together (NCC + both aggregations): the binding bound is the
+    # larger of the VALU time of their flops and the HBM time of their bytes
+    t_meas = st["ncc_ms"] + st["aggregate_wta_ref_ms"] + st["aggregate_wta_tar_ms"]
+    cf_flops = 2 * flops_per_launch + 8.0 * w.num_disp * H * (W + w.num_disp - 1)
+    cf_bytes = ncc_bytes + 2 * 4.0 * elements
+    t_valu = cf_flops / (MI355X_FP32_VALU_TFLOPS * 1e12) * 1e3
+    t_hbm = cf_bytes / (MI355X_HBM_GBS * 1e9) * 1e3
+    cost_filter = dict(stages="ncc + aggregation of both volumes", measured_ms=round(t_meas, 4),
+                       valu_bound_ms=round(t_valu, 4), hbm_bound_ms=round(t_hbm, 4),
+                       binding="alu" if t_valu >= t_hbm else "hbm",
+                       frac=round(max(t_valu, t_hbm) / t_meas, 4),
+                       frac_of_packed_peak=round(t_valu * MI355X_FP32_VALU_TFLOPS /
+                                                 MI355X_FP32_PACKED_TFLOPS / t_meas, 4))
+
     value = elements / (ms / 1e3) / 1e9
     res = {
         "metric": "G pixel·disparities/s (fwd, fwd+bwd) and fps at 1280×720, vs plain per-pair",
@@ -347,6 +361,7 @@ def run(args):
                                                    "ncc_levels")},
         "roofline": roof,
         "roofline_ncc": ncc,
+        "roofline_cost_filter": cost_filter,
     }
     if args.extra:
         res["damage_segmentation"] = damage_segmentation(args, plan, w, sc, disp_t)
