@@ -27,6 +27,9 @@ MI355X_HBM_GBS = 8000.0
 # published 157.3 TFLOP/s but is disabled in this build.
 MI355X_FP32_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 MI355X_FP32_PACKED_TFLOPS = 157.3
+# dense FP32 matrix-core rate: v_mfma_f32_16x16x4f32 is 16*16*4 FMAs per SIMD
+# every 32 cycles, 256 CUs x 4 SIMDs x 2.4 GHz
+MI355X_FP32_MFMA_TFLOPS = 157.3
 
 
 def _sha(path):
@@ -238,7 +241,7 @@ def batched(args, scenes):
                 batch_gpd_s=round(el / (t_b / 1e3) / 1e9, 3), per_pair_ms=round(t_p, 3),
                 per_pair_gpd_s=round(el / (t_p / 1e3) / 1e9, 3),
                 speedup_vs_per_pair=round(t_p / t_b, 3), equal_to_per_pair=bool(same),
-                tuning={k: b.get_tuning(k) for k in ("wg_per_cu", "agg_levels_u8",
+                tuning={k: b.get_tuning(k) for k in ("agg_engine", "wg_per_cu", "agg_levels_u8",
                                                      "agg_levels_f32")},
                 autotune_best_ms=round(tuned_ms, 3))
 
@@ -312,13 +315,26 @@ def run(args):
     flops_per_launch = 2.0 * taps * elements          # multiply-adds of Eq. (11)
     agg_s = (st["aggregate_wta_ref_ms"] + st["aggregate_wta_tar_ms"]) / 2.0 / 1e3
     achieved = flops_per_launch / agg_s / 1e12
-    src = os.path.join(ROOT, "paper_1904_06017_amd", "csrc", "bilateral_impl.h")
-    roof = dict(kernel="bilateral_kernel (aggregation + fused WTA, both volumes)",
-                bound="alu", achieved=round(achieved, 2), peak=round(MI355X_FP32_VALU_TFLOPS, 1),
-                unit="TFLOP/s", frac=round(achieved / MI355X_FP32_VALU_TFLOPS, 4),
-                frac_of_packed_peak=round(achieved / MI355X_FP32_PACKED_TFLOPS, 4),
-                flops_per_launch=flops_per_launch, avg_launch_ms=round(agg_s * 1e3, 4),
-                traffic=_traffic(src, "hbm_bytes_per_launch"))
+    engine = plan.get_tuning("agg_engine")
+    if engine == 1:
+        # matrix cores: each 4x4 pixel block multiplies over its (2R + 4)^2
+        # window union, (2R + 4)^2 / (2R + 1)^2 of the algorithmic products
+        src = os.path.join(ROOT, "paper_1904_06017_amd", "csrc", "bilateral_mfma.h")
+        union = (2 * w.bil_radius + 4) ** 2
+        roof = dict(kernel="agg_wta_mfma_kernel (aggregation + fused WTA, both volumes)",
+                    bound="mfma", achieved=round(achieved, 2), peak=MI355X_FP32_MFMA_TFLOPS,
+                    unit="TFLOP/s", frac=round(achieved / MI355X_FP32_MFMA_TFLOPS, 4),
+                    issued_frac=round(achieved * union / taps / MI355X_FP32_MFMA_TFLOPS, 4),
+                    flops_per_launch=flops_per_launch, avg_launch_ms=round(agg_s * 1e3, 4),
+                    traffic=_traffic(src, "hbm_bytes_per_launch"))
+    else:
+        src = os.path.join(ROOT, "paper_1904_06017_amd", "csrc", "bilateral_impl.h")
+        roof = dict(kernel="bilateral_kernel (aggregation + fused WTA, both volumes)",
+                    bound="alu", achieved=round(achieved, 2), peak=round(MI355X_FP32_VALU_TFLOPS, 1),
+                    unit="TFLOP/s", frac=round(achieved / MI355X_FP32_VALU_TFLOPS, 4),
+                    frac_of_packed_peak=round(achieved / MI355X_FP32_PACKED_TFLOPS, 4),
+                    flops_per_launch=flops_per_launch, avg_launch_ms=round(agg_s * 1e3, 4),
+                    traffic=_traffic(src, "hbm_bytes_per_launch"))
     # NCC stage: HBM-bound when the volume is materialised
     cw = ((W + w.num_disp - 1) + 3) & ~3
     ncc_bytes = 4.0 * w.num_disp * H * (W + w.num_disp - 1)
@@ -328,18 +344,20 @@ def run(args):
                bytes_per_launch=ncc_bytes)
 
     # cost + filter together (NCC + both aggregations): the binding bound is the
-    # larger of the VALU time of their flops and the HBM time of their bytes
+    # larger of their compute time (NCC on the vector ALU; the aggregation on
+    # the vector ALU or the matrix cores, which do not issue alongside vector
+    # ALU work on a SIMD, so the two times add) and the HBM time of their bytes
     t_meas = st["ncc_ms"] + st["aggregate_wta_ref_ms"] + st["aggregate_wta_tar_ms"]
-    cf_flops = 2 * flops_per_launch + 8.0 * w.num_disp * H * (W + w.num_disp - 1)
+    ncc_flops = 8.0 * w.num_disp * H * (W + w.num_disp - 1)
     cf_bytes = ncc_bytes + 2 * 4.0 * elements
-    t_valu = cf_flops / (MI355X_FP32_VALU_TFLOPS * 1e12) * 1e3
+    agg_peak = MI355X_FP32_MFMA_TFLOPS if engine == 1 else MI355X_FP32_VALU_TFLOPS
+    t_comp = (ncc_flops / (MI355X_FP32_VALU_TFLOPS * 1e12) +
+              2 * flops_per_launch / (agg_peak * 1e12)) * 1e3
     t_hbm = cf_bytes / (MI355X_HBM_GBS * 1e9) * 1e3
     cost_filter = dict(stages="ncc + aggregation of both volumes", measured_ms=round(t_meas, 4),
-                       valu_bound_ms=round(t_valu, 4), hbm_bound_ms=round(t_hbm, 4),
-                       binding="alu" if t_valu >= t_hbm else "hbm",
-                       frac=round(max(t_valu, t_hbm) / t_meas, 4),
-                       frac_of_packed_peak=round(t_valu * MI355X_FP32_VALU_TFLOPS /
-                                                 MI355X_FP32_PACKED_TFLOPS / t_meas, 4))
+                       compute_bound_ms=round(t_comp, 4), hbm_bound_ms=round(t_hbm, 4),
+                       binding=("mfma+alu" if engine == 1 else "alu") if t_comp >= t_hbm else "hbm",
+                       frac=round(max(t_comp, t_hbm) / t_meas, 4))
 
     value = elements / (ms / 1e3) / 1e9
     res = {
@@ -357,7 +375,7 @@ def run(args):
                    "sigma_s": w.sigma_s, "sigma_r": w.sigma_r, "perspective": True,
                    "input": "uint8", "step": "plain path + road fit/transform"},
         "stages_ms": {k: round(v, 4) for k, v in st.items()},
-        "tuning": {k: plan.get_tuning(k) for k in ("agg_levels_u8", "agg_levels_f32",
+        "tuning": {k: plan.get_tuning(k) for k in ("agg_engine", "agg_levels_u8", "agg_levels_f32",
                                                    "ncc_levels")},
         "roofline": roof,
         "roofline_ncc": ncc,

@@ -123,9 +123,13 @@ stereo_status stereo_plan_set_homography(stereo_plan_t plan, const double* H);
 
 /* ---- tuning knobs (host only) ---------------------------------------------
  * Launch-shape choices.  Keys:
+ *   "agg_engine": the kernel of the fused aggregation and selection
+ *   (stereo_match, Eq. 9-11 and 13): 1 (default) the matrix cores, 0 the
+ *   vector ALU; the two sum in different orders, so they agree to FP32
+ *   rounding (a disparity can differ at a near tie), not bit for bit;
  *   "agg_levels_u8", "agg_levels_f32": disparity levels staged per pass of
- *   the aggregation kernel for 8-bit / float guides, 8 or 16 (default 8);
- *   results are bitwise identical for every value;
+ *   the vector-ALU aggregation kernel for 8-bit / float guides, 8 or 16
+ *   (default 8); results are bitwise identical for every value;
  *   "ncc_levels": disparity levels per workgroup of the NCC cost kernel, 16,
  *   32 or 64, or 0 (default: 64, 32 or 16, the largest block the launch's
  *   levels fill); results are bitwise identical for every value;
@@ -285,8 +289,11 @@ typedef struct {
 stereo_status stereo_batch_create(const stereo_batch_item* items, int32_t n,
                                   stereo_batch_t* out);
 stereo_status stereo_batch_workspace_bytes(stereo_batch_t b, size_t* bytes);
-/* Tuning keys: "wg_per_cu" (persistent workgroups per CU, 1..8, default 2),
- * "agg_levels_u8", "agg_levels_f32" (8 or 16).  Drops an instantiated graph. */
+/* Tuning keys: "agg_engine" (as for a plan: 1 matrix cores, default, or 0
+ * vector ALU; a batch gives the same bits as its pairs' stereo_match when
+ * both use the same engine), "wg_per_cu" (persistent workgroups per CU of
+ * the vector-ALU engine, 1..8, default 2), "agg_levels_u8", "agg_levels_f32"
+ * (8 or 16).  Drops an instantiated graph. */
 stereo_status stereo_batch_set_tuning(stereo_batch_t b, const char* key, int32_t value);
 stereo_status stereo_batch_get_tuning(stereo_batch_t b, const char* key, int32_t* value);
 /* Enqueue the whole batch on `stream` (no graph).  The first call with a given

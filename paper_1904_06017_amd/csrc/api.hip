@@ -217,6 +217,11 @@ stereo_status stereo_plan_set_tuning(stereo_plan_t plan, const char* key, int32_
     (k == "agg_levels_u8" ? plan->P.agg_levels_u8 : plan->P.agg_levels_f32) = value;
     return STEREO_OK;
   }
+  if (k == "agg_engine") {
+    STEREO_REQUIRE(value == 0 || value == 1, "agg_engine must be 0 (vector ALU) or 1 (matrix cores)");
+    plan->P.agg_engine = value;
+    return STEREO_OK;
+  }
   if (k == "ncc_levels") {
     STEREO_REQUIRE(value == 0 || value == 16 || value == 32 || value == 64,
                    "ncc_levels must be 0 (automatic), 16, 32 or 64");
@@ -233,6 +238,7 @@ stereo_status stereo_plan_get_tuning(stereo_plan_t plan, const char* key, int32_
   if (k == "agg_levels_f32") { *value = plan->P.agg_levels_f32; return STEREO_OK; }
   if (k == "grad_levels") { *value = plan->P.grad_levels; return STEREO_OK; }
   if (k == "ncc_levels") { *value = plan->P.ncc_levels; return STEREO_OK; }
+  if (k == "agg_engine") { *value = plan->P.agg_engine; return STEREO_OK; }
   return fail(STEREO_ERR_INVALID_ARGUMENT, "unknown tuning key '%s'", key);
 }
 

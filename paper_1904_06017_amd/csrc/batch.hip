@@ -23,8 +23,10 @@ struct Group {
   int R;
   stereo_dtype gdt;
   int levels;
-  std::vector<int> tiles;     // (pair descriptor index, x0, y0) triples
+  std::vector<int> tiles;     // (pair descriptor index, x0, y0) triples, vector-ALU tiles
+  std::vector<int> tiles_m;   // the same over the matrix-core tiles
   size_t tiles_off;           // in the workspace
+  size_t tiles_m_off;
 };
 
 // One batched launch of a cheap stage: its jobs (pair, and for statistics
@@ -62,6 +64,7 @@ struct stereo_batch_s {
   void* bound_ws = nullptr;
   int wg_per_cu = 2;
   int levels_u8 = 8, levels_f32 = 8;
+  int engine = 1;                      // aggregation engine: 1 matrix cores, 0 vector ALU
   int cu_count = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -90,7 +93,7 @@ void build_layout(stereo_batch_s& b) {
   // queue drains with the long tiles taken first
   b.groups.clear();
   struct T { int cost, pair, vol, x0, y0; };
-  std::vector<std::vector<T>> per;
+  std::vector<std::vector<T>> per, per_m;
   auto find_group = [&](int R, stereo_dtype g) {
     for (size_t i = 0; i < b.groups.size(); ++i)
       if (b.groups[i].R == R && b.groups[i].gdt == g) return (int)i;
@@ -99,6 +102,7 @@ void build_layout(stereo_batch_s& b) {
     G.levels = g == STEREO_U8 ? b.levels_u8 : b.levels_f32;
     b.groups.push_back(G);
     per.emplace_back();
+    per_m.emplace_back();
     return (int)b.groups.size() - 1;
   };
   for (int i = 0; i < n; ++i) {
@@ -108,20 +112,24 @@ void build_layout(stereo_batch_s& b) {
       const int gi = find_group(P.R, g);
       for (int y = 0; y < P.H; y += kBilTileH)
         for (int x = 0; x < P.W; x += kBilTileW) per[gi].push_back({P.D, i, vol, x, y});
+      for (int y = 0; y < P.H; y += kMfmaTileH)
+        for (int x = 0; x < P.W; x += kMfmaTileW) per_m[gi].push_back({P.D, i, vol, x, y});
     }
   }
-  for (size_t gi = 0; gi < b.groups.size(); ++gi) {
-    std::stable_sort(per[gi].begin(), per[gi].end(),
-                     [](const T& a, const T& c) { return a.cost > c.cost; });
-    auto& tl = b.groups[gi].tiles;
+  auto table = [&](std::vector<T>& src, std::vector<int>& tl, size_t& off) {
+    std::stable_sort(src.begin(), src.end(), [](const T& a, const T& c) { return a.cost > c.cost; });
     tl.clear();
-    for (const T& t : per[gi]) {
+    for (const T& t : src) {
       tl.push_back(2 * t.pair + t.vol);
       tl.push_back(t.x0);
       tl.push_back(t.y0);
     }
-    b.groups[gi].tiles_off = o;
+    off = o;
     o = align256(o + sizeof(int) * tl.size());
+  };
+  for (size_t gi = 0; gi < b.groups.size(); ++gi) {
+    table(per[gi], b.groups[gi].tiles, b.groups[gi].tiles_off);
+    table(per_m[gi], b.groups[gi].tiles_m, b.groups[gi].tiles_m_off);
   }
   b.counter_off = o;
   o = align256(o + sizeof(unsigned int) * std::max<size_t>(1, b.groups.size()));
@@ -263,9 +271,13 @@ stereo_status bind(stereo_batch_s& b, void* ws, size_t bytes, hipStream_t s) {
     BHIP(hipMemcpyAsync(at<char>(ws, L.first_off), L.first.data(), sizeof(int) * L.first.size(),
                         hipMemcpyHostToDevice, s), "upload job prefix");
   }
-  for (const Group& G : b.groups)
+  for (const Group& G : b.groups) {
     BHIP(hipMemcpyAsync(at<char>(ws, G.tiles_off), G.tiles.data(), sizeof(int) * G.tiles.size(),
                         hipMemcpyHostToDevice, s), "upload tiles");
+    BHIP(hipMemcpyAsync(at<char>(ws, G.tiles_m_off), G.tiles_m.data(),
+                        sizeof(int) * G.tiles_m.size(), hipMemcpyHostToDevice, s),
+         "upload matrix-core tiles");
+  }
   BHIP(hipStreamSynchronize(s), "synchronise after upload");
   b.bound_ws = ws;
   return STEREO_OK;
@@ -313,10 +325,17 @@ stereo_status enqueue(stereo_batch_s& b, hipStream_t s) {
   const void* desc = at<char>(ws, b.desc_off);
   for (int g = 0; g < ng; ++g) {
     const Group& G = b.groups[g];
-    const int nt = (int)G.tiles.size() / 3;
-    const int groups = std::max(1, std::min(nt, b.cu_count * b.wg_per_cu));
-    BHIP(launch_bilateral_persistent(G.R, G.gdt, G.levels, desc, at<int>(ws, G.tiles_off), nt,
-                                     ctr + g, groups, s), "batch aggregation");
+    if (b.engine == 1) {                 // one workgroup per CU holds the whole LDS
+      const int nt = (int)G.tiles_m.size() / 3;
+      const int groups = std::max(1, std::min(nt, b.cu_count));
+      BHIP(launch_bilateral_persistent(1, G.R, G.gdt, G.levels, desc, at<int>(ws, G.tiles_m_off), nt,
+                                       ctr + g, groups, s), "batch aggregation");
+    } else {
+      const int nt = (int)G.tiles.size() / 3;
+      const int groups = std::max(1, std::min(nt, b.cu_count * b.wg_per_cu));
+      BHIP(launch_bilateral_persistent(0, G.R, G.gdt, G.levels, desc, at<int>(ws, G.tiles_off), nt,
+                                       ctr + g, groups, s), "batch aggregation");
+    }
   }
   for (const JobList& L : b.lists)
     if (L.kind == JK_LR) {
@@ -382,6 +401,9 @@ stereo_status stereo_batch_set_tuning(stereo_batch_t b, const char* key, int32_t
     BREQ(value == 8 || value == 16, "%s must be 8 or 16", key);
     (k == "agg_levels_u8" ? b->levels_u8 : b->levels_f32) = value;
     for (Group& G : b->groups) G.levels = G.gdt == STEREO_U8 ? b->levels_u8 : b->levels_f32;
+  } else if (k == "agg_engine") {
+    BREQ(value == 0 || value == 1, "agg_engine must be 0 (vector ALU) or 1 (matrix cores)");
+    b->engine = value;
   } else {
     return fail(STEREO_ERR_INVALID_ARGUMENT, "unknown batch tuning key '%s'", key);
   }
@@ -395,6 +417,7 @@ stereo_status stereo_batch_get_tuning(stereo_batch_t b, const char* key, int32_t
   if (k == "wg_per_cu") *value = b->wg_per_cu;
   else if (k == "agg_levels_u8") *value = b->levels_u8;
   else if (k == "agg_levels_f32") *value = b->levels_f32;
+  else if (k == "agg_engine") *value = b->engine;
   else return fail(STEREO_ERR_INVALID_ARGUMENT, "unknown batch tuning key '%s'", key);
   return STEREO_OK;
 }

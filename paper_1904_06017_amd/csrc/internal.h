@@ -41,6 +41,7 @@ struct Plan {
   double Hm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   int ncc_levels = 0;   // levels per NCC workgroup (16, 32 or 64; DC / 4 waves);
                         // 0: 64 / 32 / 16 by the levels of the launch
+  int agg_engine = 1;   // fused aggregation + selection: 1 matrix cores, 0 vector ALU
   // differentiable form (F32 plans): levels recomputed per backward tile and
   // the workspace regions it uses (offsets from the workspace base)
   int grad_levels = 16;
@@ -135,12 +136,15 @@ hipError_t launch_bilateral(const Plan& P, const BilArgs& a, int mode,
 // pairs: pairs = device array of per-pair descriptors (bilateral_pair), tiles
 // = device int triples (pair, x0, y0), counter = device uint zeroed before the
 // launch.  All pairs of one launch share R, the guide type and `levels`.
-hipError_t launch_bilateral_persistent(int R, stereo_dtype gdt, int levels, const void* pairs,
+// engine 1 (matrix cores): tiles of kMfmaTileW x kMfmaTileH, one workgroup
+// per CU; engine 0 (vector ALU): tiles of kBilTileW x kBilTileH.
+hipError_t launch_bilateral_persistent(int engine, int R, stereo_dtype gdt, int levels, const void* pairs,
                                        const int* tiles, int n_tiles, unsigned int* counter,
                                        int n_groups, hipStream_t s);
 size_t bilateral_pair_bytes();
 void* bilateral_pair(const Plan& P, const BilArgs& a, void* out);
 constexpr int kBilTileW = 32, kBilTileH = 32;   // pixels per aggregation tile
+constexpr int kMfmaTileW = 16, kMfmaTileH = 12; // the same on the matrix cores
 
 hipError_t launch_wta(const Plan& P, const float* E, int16_t* dint,
                       float* dsub, hipStream_t s);

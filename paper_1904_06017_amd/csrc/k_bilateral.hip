@@ -3,21 +3,21 @@
 
 namespace stereo {
 hipError_t launch_bilateral_r1(const Plan&, const BilArgs&, int, hipStream_t);
-hipError_t launch_bilateral_persistent_r1(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r1(int, stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
 hipError_t launch_bilateral_r2(const Plan&, const BilArgs&, int, hipStream_t);
-hipError_t launch_bilateral_persistent_r2(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r2(int, stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
 hipError_t launch_bilateral_r3(const Plan&, const BilArgs&, int, hipStream_t);
-hipError_t launch_bilateral_persistent_r3(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r3(int, stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
 hipError_t launch_bilateral_r4(const Plan&, const BilArgs&, int, hipStream_t);
-hipError_t launch_bilateral_persistent_r4(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r4(int, stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
 hipError_t launch_bilateral_r5(const Plan&, const BilArgs&, int, hipStream_t);
-hipError_t launch_bilateral_persistent_r5(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r5(int, stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
 hipError_t launch_bilateral_r6(const Plan&, const BilArgs&, int, hipStream_t);
-hipError_t launch_bilateral_persistent_r6(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r6(int, stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
 hipError_t launch_bilateral_r7(const Plan&, const BilArgs&, int, hipStream_t);
-hipError_t launch_bilateral_persistent_r7(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r7(int, stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
 hipError_t launch_bilateral_r8(const Plan&, const BilArgs&, int, hipStream_t);
-hipError_t launch_bilateral_persistent_r8(stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
+hipError_t launch_bilateral_persistent_r8(int, stereo_dtype, int, const void*, const int*, int, unsigned int*, int, hipStream_t);
 
 hipError_t launch_bilateral(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
   switch (P.R) {
@@ -33,18 +33,18 @@ hipError_t launch_bilateral(const Plan& P, const BilArgs& a, int mode, hipStream
   }
 }
 
-hipError_t launch_bilateral_persistent(int R, stereo_dtype gdt, int levels, const void* pairs,
+hipError_t launch_bilateral_persistent(int engine, int R, stereo_dtype gdt, int levels, const void* pairs,
                                        const int* tiles, int n_tiles, unsigned int* counter,
                                        int n_groups, hipStream_t s) {
   switch (R) {
-    case 1: return launch_bilateral_persistent_r1(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
-    case 2: return launch_bilateral_persistent_r2(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
-    case 3: return launch_bilateral_persistent_r3(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
-    case 4: return launch_bilateral_persistent_r4(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
-    case 5: return launch_bilateral_persistent_r5(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
-    case 6: return launch_bilateral_persistent_r6(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
-    case 7: return launch_bilateral_persistent_r7(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
-    case 8: return launch_bilateral_persistent_r8(gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    case 1: return launch_bilateral_persistent_r1(engine, gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    case 2: return launch_bilateral_persistent_r2(engine, gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    case 3: return launch_bilateral_persistent_r3(engine, gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    case 4: return launch_bilateral_persistent_r4(engine, gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    case 5: return launch_bilateral_persistent_r5(engine, gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    case 6: return launch_bilateral_persistent_r6(engine, gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    case 7: return launch_bilateral_persistent_r7(engine, gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
+    case 8: return launch_bilateral_persistent_r8(engine, gdt, levels, pairs, tiles, n_tiles, counter, n_groups, s);
     default: return hipErrorInvalidValue;
   }
 }

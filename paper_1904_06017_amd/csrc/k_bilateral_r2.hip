@@ -1,14 +1,16 @@
 // Aggregation kernels instantiated for window radius R = 2.
-#include "bilateral_impl.h"
+#include "bilateral_mfma.h"
 
 namespace stereo {
 hipError_t launch_bilateral_r2(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
+  if (mode == 1 && P.agg_engine == 1 && a.quad) return bilm::launch_args<2>(P, a, s);
   return bil::launch_r<2>(P, a, mode, s);
 }
-hipError_t launch_bilateral_persistent_r2(stereo_dtype gdt, int levels, const void* pairs,
+hipError_t launch_bilateral_persistent_r2(int engine, stereo_dtype gdt, int levels, const void* pairs,
                                            const int* tiles, int n_tiles, unsigned int* counter,
                                            int n_groups, hipStream_t s) {
-  return bil::launch_persistent_r<2>(gdt, levels, static_cast<const bil::BilPair*>(pairs),
-                                        tiles, n_tiles, counter, n_groups, s);
+  const bil::BilPair* p = static_cast<const bil::BilPair*>(pairs);
+  if (engine == 1) return bilm::launch_queue_r<2>(gdt, p, tiles, n_tiles, counter, n_groups, s);
+  return bil::launch_persistent_r<2>(gdt, levels, p, tiles, n_tiles, counter, n_groups, s);
 }
 }  // namespace stereo

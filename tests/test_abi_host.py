@@ -121,6 +121,10 @@ def test_tuning_keys(lib):
     assert lib.stereo_plan_set_tuning(h, b"ncc_levels", 64) == 0
     assert lib.stereo_plan_get_tuning(h, b"ncc_levels", ctypes.byref(v)) == 0 and v.value == 64
     assert lib.stereo_plan_set_tuning(h, b"ncc_levels", 48) == 1
+    assert lib.stereo_plan_get_tuning(h, b"agg_engine", ctypes.byref(v)) == 0 and v.value == 1
+    assert lib.stereo_plan_set_tuning(h, b"agg_engine", 0) == 0
+    assert lib.stereo_plan_get_tuning(h, b"agg_engine", ctypes.byref(v)) == 0 and v.value == 0
+    assert lib.stereo_plan_set_tuning(h, b"agg_engine", 2) == 1
     assert lib.stereo_plan_set_tuning(h, b"no_such_key", 8) == 1
     lib.stereo_plan_destroy(h)
 
@@ -165,3 +169,16 @@ def test_homography_argument_checks(lib):
     s, h = _create(lib, raw)
     assert lib.stereo_plan_set_homography(h, H) == 1              # needs perspective = 1
     lib.stereo_plan_destroy(h)
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built library every entry point raises: there is no CPU
+    fallback behind the Python layer."""
+    from paper_1904_06017_amd import _lib as L
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", "/nonexistent/libstereo.so")
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        L.load()
+    from paper_1904_06017_amd import api
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        api.Plan(api.make_params(64, 48, 16, delta_p=8, plane=(4, 0, 0.1)))

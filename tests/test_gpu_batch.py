@@ -54,11 +54,14 @@ def _make(pairs):
     return items
 
 
-def test_batch_equals_plain_path(small_batch):
+@pytest.mark.parametrize("engine", [1, 0], ids=["mfma", "valu"])
+def test_batch_equals_plain_path(small_batch, engine):
     items = _make(small_batch)
     b = api.Batch(items)
+    b.set_tuning("agg_engine", engine)
     outs = [{k: _host(v) for k, v in o.items()} for o in b.submit()]
     for (plan, ref, tar), o in zip(items, outs):
+        plan.set_tuning("agg_engine", engine)
         m = api.match(plan, ref, tar)
         assert np.array_equal(_host(m["dint_R"]), o["dint_R"])
         assert np.array_equal(_host(m["valid"]), o["valid"])
