@@ -44,6 +44,9 @@ constexpr int kTW = 16, kTH = 4 * kBR;  // tile in pixels
 static_assert(kTW == kMfmaTileW && kTH == kMfmaTileH, "tile size shared with the batch tables");
 constexpr int kRS = 36;                 // float4 slots per staged halo row
 constexpr float kFar = 1e30f;           // guide outside the image: zero weight
+#ifndef BILM_BANDS
+#define BILM_BANDS 1
+#endif
 
 template <int R>
 struct MGeom {
@@ -211,14 +214,32 @@ agg_wta_mfma_kernel(View one, const BilPair* __restrict__ pairs, const int* __re
   float* sc = scr + wave * (16 * 20);
   const float* prow = sc + P * 20;
 
-  // tiles of this workgroup: QUEUE = 0: tile blockIdx.x + k * gridDim.x of
-  // the one pair; QUEUE = 1: (pair, x0, y0) triples taken from a counter
-  int tx = 1, n1 = n_tiles;
+  // tiles of this workgroup.  QUEUE = 1: (pair, x0, y0) triples taken from a
+  // counter.  QUEUE = 0, the tiles of one pair: workgroup b runs on XCD b % 8
+  // (round-robin dispatch), so XCD x walks the tile columns of band x (ceil of
+  // a eighth of them) row by row with its workgroups in turn: the tiles in
+  // flight on one XCD are neighbours and share their halos in its L2.
+  int tx = 1, n1 = n_tiles, per = 0, c0 = 0, bc = 1, nb = 0;
   if (!QUEUE) {
     tx = __builtin_amdgcn_readfirstlane((one.W + kTW - 1) / kTW);
     n1 = __builtin_amdgcn_readfirstlane(tx * ((one.H + kTH - 1) / kTH));
+    if (BILM_BANDS && gridDim.x % 8 == 0) {
+      per = gridDim.x / 8;
+      const int bw = (tx + 7) / 8;
+      c0 = (blockIdx.x % 8) * bw;
+      bc = tx - c0 < bw ? (tx - c0 > 0 ? tx - c0 : 0) : bw;
+      nb = bc * (n1 / tx);
+    }
   }
-  auto arith_tile = [&](int k) -> int { return (int)blockIdx.x + (int)gridDim.x * k; };
+  auto arith_tile = [&](int k) -> int {
+    if (per) {
+      const int idx = (int)blockIdx.x / 8 + per * k;
+      if (idx >= nb) return n1;
+      const int row = __builtin_amdgcn_readfirstlane(idx / bc);
+      return row * tx + c0 + (idx - row * bc);
+    }
+    return (int)blockIdx.x + (int)gridDim.x * k;
+  };
   // descriptors are re-read where needed (scalar loads) rather than kept live
   auto resolve = [&](int t, View& v, int& x0, int& y0) {
     if (QUEUE) {
@@ -451,7 +472,8 @@ hipError_t launch_pair(const BilPair& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   const int n = ((a.W + kTW - 1) / kTW) * ((a.H + kTH - 1) / kTH);
   const int cus = cu_count_of_current_device();
-  const int grid = std::min(n, cus > 0 ? cus : 256);
+  int grid = std::min(n, cus > 0 ? cus : 256);
+  if (grid >= 8) grid -= grid % 8;               // whole XCD bands
   hipLaunchKernelGGL((agg_wta_mfma_kernel<R, GT, 0>), dim3(grid), dim3(kThreads), MGeom<R>::lds_bytes, s,
                      view_of(a), (const BilPair*)nullptr, (const int*)nullptr, 0, (unsigned int*)nullptr);
   return hipGetLastError();
