@@ -310,10 +310,14 @@ stereo_status stereo_batch_destroy(stereo_batch_t b);
 /* ---- autotuner ---------------------------------------------------------------
  * Times the launch-shape variants on the caller's inputs (HIP events, median
  * of `reps` runs, synchronous), applies the fastest and stores it in the JSON
- * file cache_path (nullable: no cache) keyed by GPU architecture and problem
- * shape; a cached choice is applied without timing.  best_ms (nullable)
- * receives the time of the chosen variant.  Results never depend on the
- * variant.  stereo_plan_autotune allocates temporary outputs (hipMalloc). */
+ * file cache_path (nullable: no cache) keyed by GPU architecture, problem
+ * shape and aggregation engine; a cached choice is applied without timing.
+ * Plans: "ncc_levels" (16, 32, 64), and with agg_engine = 0 also
+ * "agg_levels_u8" / "agg_levels_f32"; batches: with agg_engine = 0
+ * "wg_per_cu" and the levels per pass, with the matrix-core engine (no
+ * launch-shape knob) the one variant is timed.  best_ms (nullable) receives
+ * the time of the chosen variant.  Results never depend on the variant.
+ * stereo_plan_autotune allocates temporary outputs (hipMalloc). */
 stereo_status stereo_plan_autotune(stereo_plan_t plan, const void* ref, const void* tar,
                                    void* ws, size_t ws_bytes, hipStream_t stream,
                                    const char* cache_path, int32_t reps, double* best_ms);

@@ -114,9 +114,9 @@ std::string arch_name() {
 
 std::string plan_key(const Plan& P) {
   char buf[256];
-  snprintf(buf, sizeof(buf), "%s:plan:W=%d,H=%d,D=%d,r=%d,R=%d,dtype=%s,persp=%d,lr=%d",
+  snprintf(buf, sizeof(buf), "%s:plan:W=%d,H=%d,D=%d,r=%d,R=%d,dtype=%s,persp=%d,lr=%d,engine=%d",
            arch_name().c_str(), P.W, P.H, P.D, P.r, P.R, P.p.dtype == STEREO_U8 ? "u8" : "f32",
-           P.p.perspective, P.p.lr_check);
+           P.p.perspective, P.p.lr_check, P.agg_engine);
   return buf;
 }
 
@@ -161,6 +161,7 @@ stereo_status stereo_plan_autotune(stereo_plan_t plan, const void* ref, const vo
   if (it != cache.end() && it->second.count("agg_levels_u8") && it->second.count("agg_levels_f32")) {
     P.agg_levels_u8 = (int)it->second["agg_levels_u8"];
     P.agg_levels_f32 = (int)it->second["agg_levels_f32"];
+    if (it->second.count("ncc_levels")) P.ncc_levels = (int)it->second["ncc_levels"];
     if (best_ms) *best_ms = it->second.count("ms") ? it->second["ms"] : 0.0;
     return STEREO_OK;
   }
@@ -172,27 +173,40 @@ stereo_status stereo_plan_autotune(stereo_plan_t plan, const void* ref, const vo
   float* dsub = reinterpret_cast<float*>(dT + HW);
   float* disp = dsub + HW;
   uint8_t* valid = reinterpret_cast<uint8_t*>(disp + HW);
+  // the knobs of the plan's aggregation engine (levels per pass of the vector
+  // kernel; the matrix-core kernel has none) and the NCC level block: none
+  // changes a result
   double best = 1e30;
-  int bu = P.agg_levels_u8, bf = P.agg_levels_f32;
+  int bu = P.agg_levels_u8, bf = P.agg_levels_f32, bn = P.ncc_levels;
   stereo_status st = STEREO_OK;
-  for (int lu : {8, 16}) {
-    for (int lf : {8, 16}) {
-      P.agg_levels_u8 = lu;
-      P.agg_levels_f32 = lf;
-      double ms = 0.0;
-      st = time_ms(stream, reps, [&]() {
-        return stereo_match(plan, ref, tar, dR, dT, dsub, valid, disp, ws, ws_bytes, stream);
-      }, &ms);
+  const std::vector<int> lvs = P.agg_engine == 0 ? std::vector<int>{8, 16}
+                                                 : std::vector<int>{P.agg_levels_u8};
+  const std::vector<int> lfs = P.agg_engine == 0 ? std::vector<int>{8, 16}
+                                                 : std::vector<int>{P.agg_levels_f32};
+  for (int nl : {16, 32, 64}) {
+    for (int lu : lvs) {
+      for (int lf : lfs) {
+        P.agg_levels_u8 = lu;
+        P.agg_levels_f32 = lf;
+        P.ncc_levels = nl;
+        double ms = 0.0;
+        st = time_ms(stream, reps, [&]() {
+          return stereo_match(plan, ref, tar, dR, dT, dsub, valid, disp, ws, ws_bytes, stream);
+        }, &ms);
+        if (st != STEREO_OK) break;
+        if (ms < best) { best = ms; bu = lu; bf = lf; bn = nl; }
+      }
       if (st != STEREO_OK) break;
-      if (ms < best) { best = ms; bu = lu; bf = lf; }
     }
     if (st != STEREO_OK) break;
   }
   hipFree(buf);
   P.agg_levels_u8 = bu;
   P.agg_levels_f32 = bf;
+  P.ncc_levels = bn;
   if (st != STEREO_OK) return st;
-  cache[key] = Entry{{"agg_levels_u8", (double)bu}, {"agg_levels_f32", (double)bf}, {"ms", best}};
+  cache[key] = Entry{{"agg_levels_u8", (double)bu}, {"agg_levels_f32", (double)bf},
+                     {"ncc_levels", (double)bn}, {"ms", best}};
   save_cache(cache_path, cache);
   if (best_ms) *best_ms = best;
   return STEREO_OK;
@@ -223,8 +237,10 @@ stereo_status stereo_batch_autotune(stereo_batch_t b, void* ws, size_t ws_bytes,
     batch_pair_shape(b, i, shape);
     for (int k = 0; k < 6; ++k) mix((uint64_t)(uint32_t)shape[k]);
   }
+  int32_t engine = 1;
+  stereo_batch_get_tuning(b, "agg_engine", &engine);
   char kb[128];
-  snprintf(kb, sizeof(kb), "%s:batch:n=%d:%016llx", arch_name().c_str(), n,
+  snprintf(kb, sizeof(kb), "%s:batch:n=%d:engine=%d:%016llx", arch_name().c_str(), n, (int)engine,
            (unsigned long long)h);
   const std::string key = kb;
   auto cache = load_cache(cache_path);
@@ -235,11 +251,15 @@ stereo_status stereo_batch_autotune(stereo_batch_t b, void* ws, size_t ws_bytes,
     if (best_ms) *best_ms = it->second.count("ms") ? it->second["ms"] : 0.0;
     return STEREO_OK;
   }
+  // the knobs are those of the vector-ALU engine (workgroups per CU, levels
+  // per pass); with the matrix-core engine there is one variant to time
   double best = 1e30;
   int32_t bestv[3] = {cur[0], cur[1], cur[2]};
   stereo_status st = STEREO_OK;
-  for (int wg : {1, 2, 3, 4}) {
-    for (int lv : {8, 16}) {
+  const std::vector<int> wgs = engine == 0 ? std::vector<int>{1, 2, 3, 4} : std::vector<int>{cur[0]};
+  const std::vector<int> lvls = engine == 0 ? std::vector<int>{8, 16} : std::vector<int>{cur[1]};
+  for (int wg : wgs) {
+    for (int lv : lvls) {
       stereo_batch_set_tuning(b, "wg_per_cu", wg);
       stereo_batch_set_tuning(b, "agg_levels_u8", lv);
       stereo_batch_set_tuning(b, "agg_levels_f32", lv);

@@ -122,11 +122,13 @@ def test_plan_autotune_and_cache(small_batch, tmp_path):
     assert len(entries) == 1
     key = next(iter(entries))
     assert "gfx" in key and f"W={w.width}" in key
-    chosen = (plan.get_tuning("agg_levels_u8"), plan.get_tuning("agg_levels_f32"))
-    assert chosen == (int(entries[key]["agg_levels_u8"]), int(entries[key]["agg_levels_f32"]))
+    knobs = ("agg_levels_u8", "agg_levels_f32", "ncc_levels")
+    chosen = tuple(plan.get_tuning(k) for k in knobs)
+    assert chosen == tuple(int(entries[key][k]) for k in knobs)
+    assert chosen[2] in (16, 32, 64)
     plan2 = api.Plan.from_workload(w)
     api.autotune(plan2, ref, tar, cache, reps=2)        # cached: applied without timing
-    assert (plan2.get_tuning("agg_levels_u8"), plan2.get_tuning("agg_levels_f32")) == chosen
+    assert tuple(plan2.get_tuning(k) for k in knobs) == chosen
     after = {k: _host(v) for k, v in api.match(plan, ref, tar).items()}
     for k in before:
         assert np.array_equal(before[k], after[k], equal_nan=True)
