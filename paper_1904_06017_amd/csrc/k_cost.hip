@@ -100,12 +100,21 @@ warp_tracked_kernel(const T* __restrict__ tar, int64_t pitch, int W, double delt
 
 // Block statistics.  One workgroup covers 64 block centres x 16 rows; the
 // clamped input tile (16 + 2r rows x 64 + 2r columns, offset by -128) is
-// staged in LDS, then each thread forms the mean and the population
-// deviation of its blocks in two passes (mean first, then squared
-// deviations).  Stored as z = mu / sigma and isd = 1 / sigma, so that the
-// cost is 1 + zX zY - (S / n) isdX isdY; a flat block stores z = isd = 0,
-// which makes its cost exactly 1 without a branch.
+// staged in LDS.  The block sums of x and x^2 are separable: a vertical pass
+// sums 2r + 1 rows per tile column, a horizontal pass 2r + 1 of those column
+// sums per block.  Both run in FP64 (the vector FP64 rate equals the FP32
+// one here): x^2 of an FP32 value is exact in FP64 and sums of at most 289
+// of them lose nothing that matters, so the one-pass variance
+// q / n - (s / n)^2 carries no cancellation error.  Stored as z = mu / sigma
+// and isd = 1 / sigma (rounded to FP32 once), so that the cost is
+// 1 + zX zY - (S / n) isdX isdY; a flat block (variance below kFlatVar)
+// stores z = isd = 0, which makes its cost exactly 1 without a branch.
 constexpr int ST_TX = 64, ST_TY = 16;
+
+__host__ __device__ constexpr size_t stats_lds_bytes(int r) {
+  return sizeof(float) * (size_t)(ST_TX + 2 * r) * (ST_TY + 2 * r) +
+         2 * sizeof(double) * (size_t)ST_TY * (ST_TX + 2 * r);
+}
 
 template <typename T>
 __device__ __forceinline__ void block_stats_body(const T* __restrict__ img, int64_t pitch,
@@ -122,28 +131,39 @@ __device__ __forceinline__ void block_stats_body(const T* __restrict__ img, int6
     const int gx = min(max(xc0 - r + xx, 0), W - 1);
     tile[i] = ld(img + (int64_t)gy * pitch + gx) - kOffset;
   }
+  // column sums of the block rows of each output row: [ST_TY][tw], x and x^2
+  double* cs = reinterpret_cast<double*>(tile + tw * th);
+  double* cq = cs + ST_TY * tw;
   __syncthreads();
-  const int n = (2 * r + 1) * (2 * r + 1);
-  const float inv_n = 1.0f / (float)n;
+  const int k = 2 * r + 1;
+  for (int o = threadIdx.x; o < ST_TY * tw; o += blockDim.x) {
+    const int ty = o / tw, c = o - ty * tw;
+    double sx = 0.0, sq = 0.0;
+    for (int i = 0; i < k; ++i) {
+      const double v = (double)tile[(ty + i) * tw + c];
+      sx += v;
+      sq = fma(v, v, sq);
+    }
+    cs[o] = sx;
+    cq[o] = sq;
+  }
+  __syncthreads();
+  const double inv_n = 1.0 / (double)(k * k);
   for (int o = threadIdx.x; o < ST_TX * ST_TY; o += blockDim.x) {
     const int ty = o / ST_TX, tx = o - ty * ST_TX;
     const int xi = bx * ST_TX + tx;               // map column index
     const int y = y0 + ty;
     if (xi >= SW || y >= H) continue;
-    float s = 0.0f;
-    for (int i = 0; i <= 2 * r; ++i)
-      for (int j = 0; j <= 2 * r; ++j) s += tile[(ty + i) * tw + tx + j];
-    const float m = s * inv_n;
-    float q = 0.0f;
-    for (int i = 0; i <= 2 * r; ++i)
-      for (int j = 0; j <= 2 * r; ++j) {
-        const float e = tile[(ty + i) * tw + tx + j] - m;
-        q = fmaf(e, e, q);
-      }
-    const float var = q * inv_n;
-    const float is = (var < kFlatVar) ? 0.0f : 1.0f / sqrtf(var);
-    zmap[(int64_t)y * SW + xi] = m * is;
-    isd[(int64_t)y * SW + xi] = is;
+    double sx = 0.0, sq = 0.0;
+    for (int j = 0; j < k; ++j) {
+      sx += cs[ty * tw + tx + j];
+      sq += cq[ty * tw + tx + j];
+    }
+    const double m = sx * inv_n;
+    const double var = fma(-m, m, sq * inv_n);
+    const double is = (var < (double)kFlatVar) ? 0.0 : 1.0 / sqrt(var);
+    zmap[(int64_t)y * SW + xi] = (float)(m * is);
+    isd[(int64_t)y * SW + xi] = (float)is;
   }
 }
 
@@ -467,7 +487,7 @@ hipError_t launch_warp_jobs(stereo_dtype dt, const WarpJob* jobs, const int* fir
 hipError_t launch_stats_jobs(stereo_dtype dt, const StatsJob* jobs, const int* first, int n,
                              int blocks, int max_r, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  const size_t lds = sizeof(float) * (ST_TX + 2 * max_r) * (ST_TY + 2 * max_r);
+  const size_t lds = stats_lds_bytes(max_r);
   if (dt == STEREO_U8)
     hipLaunchKernelGGL(stats_jobs_kernel<uint8_t>, dim3(blocks), dim3(256), lds, s, jobs, first,
                        n);
@@ -564,7 +584,7 @@ hipError_t launch_block_stats(const Plan& P, const void* img, stereo_dtype dt,
                               int64_t pitch, float* z, float* isd, hipStream_t s) {
   const int SW = P.W + 2 * P.r;
   dim3 grid((SW + ST_TX - 1) / ST_TX, (P.H + ST_TY - 1) / ST_TY);
-  const size_t lds = sizeof(float) * (ST_TX + 2 * P.r) * (ST_TY + 2 * P.r);
+  const size_t lds = stats_lds_bytes(P.r);
   if (dt == STEREO_U8)
     hipLaunchKernelGGL(block_stats_kernel<uint8_t>, grid, dim3(256), lds, s,
                        (const uint8_t*)img, pitch, P.W, P.H, P.r, z, isd);
