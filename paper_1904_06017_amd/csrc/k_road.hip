@@ -31,16 +31,20 @@ road_moments_kernel(const float* __restrict__ disp, const uint8_t* __restrict__ 
   double a[kMom];
 #pragma unroll
   for (int j = 0; j < kMom; ++j) a[j] = 0.0;
-  const int64_t HW = (int64_t)W * H;
-  for (int64_t p = (int64_t)blockIdx.x * kRoadThreads + threadIdx.x; p < HW;
-       p += (int64_t)gridDim.x * kRoadThreads) {
-    const float df = disp[p];
-    if (!(df == df) || isinf(df)) continue;          // NaN / inf: not a disparity
-    if (mask && !mask[p]) continue;
-    const double d = df;
-    const double v = (double)(p / W), u = (double)(p - (p / W) * W);
-    a[0] += 1.0; a[1] += u; a[2] += v; a[3] += u * u; a[4] += u * v;
-    a[5] += v * v; a[6] += d; a[7] += d * d; a[8] += d * u; a[9] += d * v;
+  // rows by block, columns by thread: no division per pixel
+  for (int y = blockIdx.x; y < H; y += gridDim.x) {
+    const float* drow = disp + (int64_t)y * W;
+    const uint8_t* mrow = mask ? mask + (int64_t)y * W : nullptr;
+    const double v = (double)y;
+    for (int x = threadIdx.x; x < W; x += kRoadThreads) {
+      const float df = drow[x];
+      if (!(df == df) || isinf(df)) continue;        // NaN / inf: not a disparity
+      if (mrow && !mrow[x]) continue;
+      const double d = df;
+      const double u = (double)x;
+      a[0] += 1.0; a[1] += u; a[2] += v; a[3] += u * u; a[4] += u * v;
+      a[5] += v * v; a[6] += d; a[7] += d * d; a[8] += d * u; a[9] += d * v;
+    }
   }
 #pragma unroll
   for (int j = 0; j < kMom; ++j) red[j][threadIdx.x] = a[j];
