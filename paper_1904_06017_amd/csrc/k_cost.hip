@@ -185,8 +185,12 @@ block_stats_kernel(const T* __restrict__ img, int64_t pitch, int W, int H, int r
 // register ring; the block sum is the fixed-order sum of that ring
 // (i = -r..r).  Every output is the same expression whatever the tiling.
 //
-// The unshifted operand A (X' for anchor 0, Y' for anchor 1) and the
-// level-shifted operand B are staged in LDS with clamped reads.
+// The unshifted operand A (X' for anchor 0, Y' for anchor 1), the
+// level-shifted operand B and the B side's statistics of the workgroup's
+// output rows (z and 1/sd at the shifted block centres: one contiguous column
+// range per row) are staged in LDS with clamped reads.  A wave's NC_DW
+// levels read overlapping windows of the same B row: one window of
+// K + NC_DW - 1 values serves them all.
 constexpr int NC_TX = 64, NC_TY = 32, NC_DC = 16, NC_DW = 4;
 // NC_DC is the default level block; a workgroup of DC levels has DC / 4 waves.
 
@@ -196,7 +200,9 @@ struct NccGeom {
   static constexpr int ROWS = NC_TY + 2 * r;
   static constexpr int AW = NC_TX + 2 * r;
   static constexpr int BW = NC_TX + 2 * r + DC - 1;
-  static constexpr size_t lds_bytes = sizeof(float) * (size_t)ROWS * (AW + BW);
+  static constexpr int ZW = NC_TX + DC - 1;         // B-side statistics per output row
+  static constexpr size_t lds_bytes =
+      sizeof(float) * ((size_t)ROWS * (AW + BW) + 2 * (size_t)NC_TY * ZW);
 };
 
 // QUAD = 1 writes the level-quad-interleaved layout [levels/4][H][pitch]
@@ -218,6 +224,8 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
   constexpr int K = G::K;
   float* As = sm;                         // [ROWS][AW]
   float* Bs = sm + G::ROWS * G::AW;       // [ROWS][BW]
+  float* Zs = Bs + G::ROWS * G::BW;       // [NC_TY][ZW]: z of the B side
+  float* Is = Zs + NC_TY * G::ZW;         // [NC_TY][ZW]: 1/sd of the B side
   const int x0 = bx * NC_TX;
   const int y0 = by * NC_TY;
   const int d0 = d_first + bz * DC;
@@ -239,6 +247,21 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
                                    : ld(ref + (int64_t)gy * ref_pitch + gxa) - kOffset;
     }
   }
+  // B-side statistics: entry c of output row t is the block centred at image
+  // column zxo + c (clamped to the map's [-r, W - 1 + r]), the centre that
+  // level offset boff reads for lane c - boff
+  {
+    const int zxo = anchor ? x0 + d0 : x0 - d0 - (DC - 1);
+    const float* zm = anchor ? zX : zY;
+    const float* im = anchor ? isdX : isdY;
+    for (int i = threadIdx.x; i < NC_TY * G::ZW; i += blockDim.x) {
+      const int t = i / G::ZW, c = i - t * G::ZW;
+      const int64_t rowo = (int64_t)min(y0 + t, H - 1) * SW;
+      const int cb = min(max(zxo + c, -r), W - 1 + r) + r;
+      Zs[i] = zm[rowo + cb];
+      Is[i] = im[rowo + cb];
+    }
+  }
   __syncthreads();
 
   const int lane = threadIdx.x & 63;
@@ -250,6 +273,7 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
     const int dc = wave * NC_DW + k;
     boff[k] = anchor ? dc : (DC - 1 - dc);
   }
+  const int bmin = anchor ? boff[0] : boff[NC_DW - 1];
   const float inv_n = 1.0f / (float)(K * K);
   float ring[NC_DW][K];
 #pragma unroll
@@ -266,12 +290,17 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
         float a[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) a[j] = As[yy * G::AW + lane + j];
+        // window of the wave's levels: level k reads bw[boff[k] - bmin + j]
+        float bw[K + NC_DW - 1];
+        const float* bw0 = Bs + yy * G::BW + lane + bmin;
+#pragma unroll
+        for (int j = 0; j < K + NC_DW - 1; ++j) bw[j] = bw0[j];
 #pragma unroll
         for (int k = 0; k < NC_DW; ++k) {
-          const float* brow = Bs + yy * G::BW + lane + boff[k];
-          float h = a[0] * brow[0];
+          const int o = anchor ? k : NC_DW - 1 - k;       // boff[k] - bmin
+          float h = a[0] * bw[o];
 #pragma unroll
-          for (int j = 1; j < K; ++j) h = fmaf(a[j], brow[j], h);
+          for (int j = 1; j < K; ++j) h = fmaf(a[j], bw[o + j], h);
           ring[k][s] = h;
         }
         const int y = y0 + yy - 2 * r;        // output row completed by this input row
@@ -289,9 +318,9 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
             float S = ring[k][(s + 1) % K];
 #pragma unroll
             for (int i = 2; i <= K; ++i) S += ring[k][(s + i) % K];
-            const int cb = min(max(anchor ? x + d : x - d, -r), W - 1 + r) + r;
-            const float zB = anchor ? zX[rowo + cb] : zY[rowo + cb];
-            const float iB = anchor ? isdX[rowo + cb] : isdY[rowo + cb];
+            const int zi = (yy - 2 * r) * G::ZW + lane + boff[k];
+            const float zB = Zs[zi];
+            const float iB = Is[zi];
             cq[k] = fmaf(-S * iA, iB, fmaf(zA, zB, 1.0f));
             if (!QUAD)
               C[(int64_t)(d - d_first) * out_slice + (int64_t)y * out_pitch + x] = cq[k];
@@ -372,6 +401,22 @@ ncc_jobs_kernel(const NccJob* __restrict__ jobs, const int* __restrict__ first, 
                        J.out_slice, J.anchor, sm, rem % J.gx, rem / J.gx, bz);
 }
 
+// Dynamic LDS above the 64 KB default (large radii at 64 levels), set once
+// per kernel instantiation.
+template <int r, typename T, int QUAD, int DC, int JOBS>
+hipError_t ncc_allow_lds() {
+  static bool done = false;
+  constexpr size_t bytes = NccGeom<r, DC>::lds_bytes;
+  if (!done && bytes > 64 * 1024) {
+    const void* k = JOBS ? (const void*)ncc_jobs_kernel<r, T, QUAD, DC>
+                         : (const void*)ncc_kernel<r, T, QUAD, DC>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  done = true;
+  return hipSuccess;
+}
+
 template <int r, typename T, int DC>
 hipError_t launch_ncc_rdc(const Plan& P, const T* ref, const float* tar_w, const float* zX,
                           const float* isdX, const float* zY, const float* isdY, float* C,
@@ -379,6 +424,8 @@ hipError_t launch_ncc_rdc(const Plan& P, const T* ref, const float* tar_w, const
                           int d_first, int d_end, int quad, hipStream_t s) {
   dim3 grid((out_w + NC_TX - 1) / NC_TX, (P.H + NC_TY - 1) / NC_TY,
             (d_end - d_first + DC - 1) / DC);
+  hipError_t e = quad ? ncc_allow_lds<r, T, 1, DC, 0>() : ncc_allow_lds<r, T, 0, DC, 0>();
+  if (e != hipSuccess) return e;
   if (quad)
     hipLaunchKernelGGL((ncc_kernel<r, T, 1, DC>), grid, dim3(16 * DC),
                        (NccGeom<r, DC>::lds_bytes), s, ref, P.p.pitch_ref, tar_w, P.W, P.H,
@@ -500,6 +547,8 @@ namespace {
 template <int r, typename T, int DC>
 hipError_t ncc_jobs_rdc(int quad, const NccJob* jobs, const int* first, int n, int blocks,
                         hipStream_t s) {
+  hipError_t e = quad ? ncc_allow_lds<r, T, 1, DC, 1>() : ncc_allow_lds<r, T, 0, DC, 1>();
+  if (e != hipSuccess) return e;
   if (quad)
     hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 1, DC>), dim3(blocks), dim3(16 * DC),
                        (NccGeom<r, DC>::lds_bytes), s, jobs, first, n);
