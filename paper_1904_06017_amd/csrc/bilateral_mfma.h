@@ -1,5 +1,5 @@
-// Bilateral aggregation fused with winner-take-all selection and sub-pixel
-// refinement (Eq. 9, 10, 11 and 13) on the matrix cores.
+// Bilateral cost aggregation, Eqs. (10)-(11), fused with winner-take-all
+// selection and sub-pixel refinement (Sec. 3.2.2, Eq. 13), on the matrix cores.
 //
 // For one 4x4 block of pixels p and 16 levels d, the aggregated costs are the
 // matrix product E[p][d] = sum_q w(p, q) C(q, d) over the positions q of the
@@ -14,9 +14,10 @@
 // A workgroup (12 waves) owns a 16 x 12 pixel tile and walks the levels in
 // passes of 16.  Each pass's halo slab (4 level quads x halo rows x 36 float4
 // slots) is copied global -> LDS by direct-to-LDS loads into one of two
-// buffers while the other is being multiplied, one barrier per pass.  Tiles at
-// the image border (or a partial last pass) stage through registers with
-// every bound checked instead.  The kernel is persistent: one workgroup per CU
+// buffers while the other is being multiplied, one barrier per pass (a last
+// pass with fewer than 16 levels copies the quads that hold a level below D).
+// Tiles at the image border stage through registers with every bound checked
+// instead.  The kernel is persistent: one workgroup per CU
 // takes tiles in turn and prefetches the next tile's first slab and guide
 // during its current tile's last pass.
 //
@@ -44,9 +45,6 @@ constexpr int kTW = 16, kTH = 4 * kBR;  // tile in pixels
 static_assert(kTW == kMfmaTileW && kTH == kMfmaTileH, "tile size shared with the batch tables");
 constexpr int kRS = 36;                 // float4 slots per staged halo row
 constexpr float kFar = 1e30f;           // guide outside the image: zero weight
-#ifndef BILM_BANDS
-#define BILM_BANDS 1
-#endif
 
 template <int R>
 struct MGeom {
@@ -223,7 +221,7 @@ agg_wta_mfma_kernel(View one, const BilPair* __restrict__ pairs, const int* __re
   if (!QUEUE) {
     tx = __builtin_amdgcn_readfirstlane((one.W + kTW - 1) / kTW);
     n1 = __builtin_amdgcn_readfirstlane(tx * ((one.H + kTH - 1) / kTH));
-    if (BILM_BANDS && gridDim.x % 8 == 0) {
+    if (gridDim.x % 8 == 0) {
       per = gridDim.x / 8;
       const int bw = (tx + 7) / 8;
       c0 = (blockIdx.x % 8) * bw;
