@@ -38,6 +38,10 @@ __device__ __forceinline__ void fix_add(unsigned long long* dst, double v) {
 
 // After all tiles: B1(x) = sum_q w (G(x) - G(q)), B2(x) = sum_q w (G(q) - G(x)) a_q / W_q,
 // dG(x) = 2/sigma_r^2 [ -(A1 - a_x B1) / W_x + (A2 - B2) ];  out = gX + dG.
+// A workgroup covers GF_TX x GF_TY pixels; the guide and a_q / W_q of the
+// tile and its R-halo (R <= 8) are staged in LDS once, the taps read them
+// there (same expressions, same tap order as a per-pixel gather).
+constexpr int GF_TX = 32, GF_TY = 8, GF_RMAX = 8;
 template <typename GT>
 __global__ void __launch_bounds__(kT)
 guide_finish_kernel(const GT* __restrict__ g, int64_t gpitch, const float* __restrict__ Wp,
@@ -45,22 +49,36 @@ guide_finish_kernel(const GT* __restrict__ g, int64_t gpitch, const float* __res
                     const float* __restrict__ A2, const float* __restrict__ gX, int W, int H,
                     int R, float ks2, float kr2, float two_over_sr2,
                     float* __restrict__ out) {
-  const int x = blockIdx.x * kT + threadIdx.x, y = blockIdx.y;
-  if (x >= W) return;
+  __shared__ float gs[(GF_TY + 2 * GF_RMAX) * (GF_TX + 2 * GF_RMAX)];
+  __shared__ float rs[(GF_TY + 2 * GF_RMAX) * (GF_TX + 2 * GF_RMAX)];
+  const int HWD = GF_TX + 2 * R, HHT = GF_TY + 2 * R;
+  const int x0 = blockIdx.x * GF_TX, y0 = blockIdx.y * GF_TY;
+  for (int i = threadIdx.x; i < HWD * HHT; i += kT) {
+    const int yy = i / HWD, xx = i - yy * HWD;
+    const int qy = y0 - R + yy, qx = x0 - R + xx;
+    const bool in = qy >= 0 && qy < H && qx >= 0 && qx < W;
+    const int64_t q = (int64_t)qy * W + qx;
+    gs[i] = in ? ldf(g + (int64_t)qy * gpitch + qx) : 0.0f;
+    rs[i] = in ? aP[q] / Wp[q] : 0.0f;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % GF_TX, ty = threadIdx.x / GF_TX;
+  const int x = x0 + tx, y = y0 + ty;
+  if (x >= W || y >= H) return;
   const int64_t p = (int64_t)y * W + x;
-  const float gx = ldf(g + (int64_t)y * gpitch + x);
+  const float gx = gs[(ty + R) * HWD + tx + R];
   float b1 = 0.0f, b2 = 0.0f;
   for (int dy = -R; dy <= R; ++dy) {
     const int qy = y + dy;
     if (qy < 0 || qy >= H) continue;
+    const int rowo = (ty + R + dy) * HWD + tx + R;
     for (int dx = -R; dx <= R; ++dx) {
       const int qx = x + dx;
       if (qx < 0 || qx >= W) continue;
-      const int64_t q = (int64_t)qy * W + qx;
-      const float dg = gx - ldf(g + (int64_t)qy * gpitch + qx);
+      const float dg = gx - gs[rowo + dx];
       const float w = __builtin_amdgcn_exp2f(-(float)(dx * dx + dy * dy) * ks2 - dg * dg * kr2);
       b1 = fmaf(w, dg, b1);
-      b2 = fmaf(-w * dg, aP[q] / Wp[q], b2);
+      b2 = fmaf(-w * dg, rs[rowo + dx], b2);
     }
   }
   const float dG = two_over_sr2 * (-(A1[p] - aP[p] * b1) / Wp[p] + (A2[p] - b2));
@@ -92,6 +110,7 @@ ncc_coef_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
   const float iX = isdX[ro + x + r];
   const float mX = iX != 0.0f ? zX[ro + x + r] / iX : 0.0f;
   float sb = Sb[p], sbm = SbmX[p], sam = SamY[p];
+  #pragma unroll 4
   for (int t = 0; t < nlev; ++t) {
     const int d = d_first + t;
     const int cy = max(x - d, -r) + r;
@@ -136,6 +155,7 @@ ncc_shear_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
   const float mY = iY != 0.0f ? zY[ro + cy] / iY : 0.0f;
   const int64_t q = (int64_t)y * WY + mi;
   float sax = SaX[q], sg = Sg[q];
+  #pragma unroll 4
   for (int t = 0; t < nlev; ++t) {
     const int x = m + d_first + t;
     if (x < 0 || x >= W) continue;
@@ -175,6 +195,7 @@ box_kernel(const float* __restrict__ F, int W, int H, float* __restrict__ B) {
   const int vx0 = blockIdx.x * BX_TX - r;          // first virtual column (image coords)
   const int vy0 = blockIdx.y * BX_TY - r;          // first virtual row (image coords)
   const int ix0 = vx0 - r, iy0 = vy0 - r;          // first input column / row
+#pragma unroll 6
   for (int i = threadIdx.x; i < THI * TWI; i += 64) {
     const int yy = i / TWI, xx = i - yy * TWI;
     const int iy = iy0 + yy, ix = ix0 + xx;
@@ -218,6 +239,7 @@ assemble_x_kernel(const float* __restrict__ Ba, const float* __restrict__ tarw, 
   const int64_t jv = (int64_t)vy * WV + vx;
   const int64_t HVWV = (int64_t)HV * WV;
   float acc = 0.0f;
+  #pragma unroll 4
   for (int t = 0; t < nlev; ++t) {
     const int xs = clampi(vx - r - (d_first + t), 0, W - 1);
     acc = fmaf(tarw[(int64_t)y * W + xs] - kOffset, Ba[t * HVWV + jv], acc);
@@ -238,6 +260,7 @@ assemble_y_kernel(const float* __restrict__ Ba, const T* __restrict__ ref, int64
   const int y = clampi(vy - r, 0, H - 1);
   const int64_t HVWV = (int64_t)HV * WVX;
   float acc = 0.0f;
+  #pragma unroll 4
   for (int t = 0; t < nlev; ++t) {
     const int jx = kx + d_first + t;                                // virtual X column
     if (jx < -r || jx >= W + r) continue;
@@ -709,7 +732,8 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
          dim3(256), 0, stream, BSY, BSY + HVWVY, BSY + 2 * HVWVY, tarw, W, H, D, r, gYv);
   LAUNCH("fold", fold_kernel, rows, dim3(256), 0, stream, gXv, W, H, r, r, gX);
   LAUNCH("fold", fold_kernel, rows, dim3(256), 0, stream, gYv, W, H, r, D - 1 + r, gtarw);
-  LAUNCH("guide gradient", guide_finish_kernel<float>, rows, dim3(256), 0, stream, ref,
+  LAUNCH("guide gradient", guide_finish_kernel<float>,
+         dim3((W + GF_TX - 1) / GF_TX, (H + GF_TY - 1) / GF_TY), dim3(256), 0, stream, ref,
          P.p.pitch_ref, Wp, aP, A1, A2, gX, W, H, P.R, c.ks2, c.kr2,
          (float)(2.0 / ((double)P.p.sigma_r * P.p.sigma_r)), grad_ref);
   LAUNCH("warp adjoint", warp_adjoint_kernel<float>, rows, dim3(256), 0, stream, tar,
