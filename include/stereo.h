@@ -124,9 +124,10 @@ stereo_status stereo_plan_set_homography(stereo_plan_t plan, const double* H);
 /* ---- tuning knobs (host only) ---------------------------------------------
  * Launch-shape choices.  Keys:
  *   "agg_engine": the kernel of the fused aggregation and selection
- *   (stereo_match, Eq. 9-11 and 13): 1 (default) the matrix cores, 0 the
- *   vector ALU; the two sum in different orders, so they agree to FP32
- *   rounding (a disparity can differ at a near tie), not bit for bit;
+ *   (stereo_match, Eq. 9-11 and 13) and of the soft-argmin forward
+ *   (stereo_soft_forward): 1 (default) the matrix cores, 0 the vector ALU;
+ *   the two sum in different orders, so they agree to FP32 rounding (a
+ *   disparity can differ at a near tie), not bit for bit;
  *   "agg_levels_u8", "agg_levels_f32": disparity levels staged per pass of
  *   the vector-ALU aggregation kernel for 8-bit / float guides, 8 or 16
  *   (default 8); results are bitwise identical for every value;

@@ -78,8 +78,14 @@ struct View {
   int64_t g_pitch;
   int W, H, D;
   float ks2, kr2;
-  int16_t* dint;
+  int16_t* dint;                  // selection (mode 1)
   float* dsub;
+  float* sm_m;                    // soft-argmin (mode 2): max_d(-E/T), log Z,
+  float* sm_logZ;                 // soft level and the shifted disparity
+  float* sm_dh;
+  float* disp;
+  float invT;
+  double delta_p, c0, c1, c2;
 };
 
 __host__ __device__ inline View view_of(const BilPair& a) {
@@ -95,6 +101,13 @@ __host__ __device__ inline View view_of(const BilPair& a) {
   v.kr2 = a.kr2;
   v.dint = a.o.dint;
   v.dsub = a.o.dsub;
+  v.sm_m = a.o.sm_m;
+  v.sm_logZ = a.o.sm_logZ;
+  v.sm_dh = a.o.sm_dh;
+  v.disp = a.o.disp;
+  v.invT = a.o.invT;
+  v.delta_p = a.o.delta_p;
+  v.c0 = a.o.c0; v.c1 = a.o.c1; v.c2 = a.o.c2;
   return v;
 }
 
@@ -191,7 +204,16 @@ __device__ __forceinline__ void guide_store(float* gs, const float (&g)[MGeom<R>
   }
 }
 
-template <int R, typename GT, int QUEUE>
+// A float from another lane of the quad (DPP quad permutation CTL).
+template <int CTL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTL, 0xF, 0xF, false));
+}
+
+// MODE 1: winner-take-all and the parabola (Eq. 13) -> dint, dsub.  MODE 2:
+// the soft-argmin head over the normalised costs (P = softmax_d(-E/T)) -> the
+// soft level, its state (max, log Z) and the shifted disparity.
+template <int R, typename GT, int QUEUE, int MODE>
 __global__ void __launch_bounds__(kThreads, 1)
 agg_wta_mfma_kernel(View one, const BilPair* __restrict__ pairs, const int* __restrict__ tiles,
                     int n_tiles, unsigned int* __restrict__ counter) {
@@ -310,6 +332,21 @@ agg_wta_mfma_kernel(View one, const BilPair* __restrict__ pairs, const int* __re
         __builtin_amdgcn_sched_barrier(0);
       }
     }
+    // soft-argmin: 1 / W_p of selection pixel P (W_p = sum of its weights:
+    // a lane's K-groups, then the four lanes of pixel li)
+    float rinvP = 1.0f, zscale = 0.0f;
+    if constexpr (MODE == 2) {
+      View cv;
+      int cx0, cy0;
+      resolve(cur, cv, cx0, cy0);
+      zscale = -cv.invT * 1.4426950408889634f;
+      float ws = 0.0f;
+#pragma unroll
+      for (int kb = 0; kb < NB * NB; ++kb) ws += wv[kb];
+      ws += __shfl_xor(ws, 16);
+      ws += __shfl_xor(ws, 32);
+      rinvP = 1.0f / __shfl(ws, P);
+    }
     __syncthreads();                             // publishes s_next
     const int nxt = QUEUE ? __builtin_amdgcn_readfirstlane(s_next) : arith_tile(k + 1);
     const bool has_next = nxt < n1;
@@ -317,6 +354,10 @@ agg_wta_mfma_kernel(View one, const BilPair* __restrict__ pairs, const int* __re
     float bestE = 3.402823466e38f, Em = 0.f, Ep = 0.f, lastE = 0.f;
     int bestD = 0;
     bool pending = false;
+    // soft-argmin state in base-2 exponents z = -E log2(e) / T: running max,
+    // Z = sum_d 2^(z - max), S = sum_d d 2^(z - max)
+    constexpr float kNeg = -3.402823466e38f;
+    float mr = kNeg, Zr = 0.0f, Sr = 0.0f;
     int D, passes;
     {
       View cv;
@@ -375,7 +416,7 @@ agg_wta_mfma_kernel(View one, const BilPair* __restrict__ pairs, const int* __re
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       // first minimum over the pass: a quad of lanes per pixel, four levels
       // per lane, then merged across the quad (lower level wins ties)
-      {
+      if constexpr (MODE == 1) {
         const float4 e4 = *reinterpret_cast<const float4*>(prow + 4 * Q);
         const int nvl = D - d0 - 4 * Q;
         const float inf = __builtin_inff();
@@ -408,13 +449,58 @@ agg_wta_mfma_kernel(View one, const BilPair* __restrict__ pairs, const int* __re
           pending = false;
         }
         lastE = prow[D - d0 < 16 ? D - d0 - 1 : 15];
+      } else {
+        // soft-argmin over the pass: per lane over its four levels, then the
+        // quad and the running state by max-rescaled sums
+        const float4 e4 = *reinterpret_cast<const float4*>(prow + 4 * Q);
+        const int nvl = D - d0 - 4 * Q;
+        const float zv[4] = {nvl > 0 ? e4.x * rinvP * zscale : kNeg, nvl > 1 ? e4.y * rinvP * zscale : kNeg,
+                             nvl > 2 ? e4.z * rinvP * zscale : kNeg, nvl > 3 ? e4.w * rinvP * zscale : kNeg};
+        float m = fmaxf(fmaxf(zv[0], zv[1]), fmaxf(zv[2], zv[3]));
+        float Zl = 0.0f, Sl = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float e = nvl > j ? __builtin_amdgcn_exp2f(zv[j] - m) : 0.0f;
+          Zl += e;
+          Sl = fmaf((float)(d0 + 4 * Q + j), e, Sl);
+        }
+        auto merge = [&](float om, float oZ, float oS) {
+          const float M = fmaxf(m, om);
+          const float a = __builtin_amdgcn_exp2f(m - M), b = __builtin_amdgcn_exp2f(om - M);
+          Zl = fmaf(Zl, a, oZ * b);
+          Sl = fmaf(Sl, a, oS * b);
+          m = M;
+        };
+        merge(dpp_f<0xB1>(m), dpp_f<0xB1>(Zl), dpp_f<0xB1>(Sl));
+        merge(dpp_f<0x4E>(m), dpp_f<0x4E>(Zl), dpp_f<0x4E>(Sl));
+        merge(mr, Zr, Sr);
+        mr = m; Zr = Zl; Sr = Sl;
       }
       if (last && has_next) guide_store<R>(gpar ? gbuf0 : gbuf1, gq);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
       par ^= 1;
     }
-    if (Q == 0) {
+    if (MODE == 2 && Q == 0) {
+      // soft level, the saved state (m, log Z) in natural units, and the
+      // shift back D = dh - delta_p + d_road(u - dh + delta_p, v)
+      View cv;
+      int cx0, cy0;
+      resolve(cur, cv, cx0, cy0);
+      const int py = cy0 + 4 * by + (P >> 2), px = cx0 + 4 * bx + (P & 3);
+      if (py < cv.H && px < cv.W) {
+        const int64_t pix = (int64_t)py * cv.W + px;
+        const float ln2 = 0.6931471805599453f;
+        const float dh = Sr / Zr;
+        cv.sm_m[pix] = mr * ln2;
+        cv.sm_logZ[pix] = __builtin_amdgcn_logf(Zr) * ln2;
+        cv.sm_dh[pix] = dh;
+        const double dd = dh;
+        cv.disp[pix] = (float)(dd - cv.delta_p + (cv.c0 + cv.c1 * ((double)px - dd + cv.delta_p) +
+                                                  cv.c2 * (double)py));
+      }
+    }
+    if (MODE == 1 && Q == 0) {
       View cv;
       int cx0, cy0;
       resolve(cur, cv, cx0, cy0);
@@ -449,11 +535,11 @@ inline int cu_count_of_current_device() {
   return cache[dev];
 }
 
-template <int R, typename GT, int QUEUE>
+template <int R, typename GT, int QUEUE, int MODE>
 hipError_t set_lds_attr() {
   static bool done = false;
   if (!done) {
-    hipError_t e = hipFuncSetAttribute((const void*)agg_wta_mfma_kernel<R, GT, QUEUE>,
+    hipError_t e = hipFuncSetAttribute((const void*)agg_wta_mfma_kernel<R, GT, QUEUE, MODE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)MGeom<R>::lds_bytes);
     if (e != hipSuccess) return e;
@@ -463,16 +549,16 @@ hipError_t set_lds_attr() {
 }
 
 // One pair (quad-layout volume): persistent, one workgroup per CU.
-template <int R, typename GT>
+template <int R, typename GT, int MODE>
 hipError_t launch_pair(const BilPair& a, hipStream_t s) {
   if (!a.quad) return hipErrorInvalidValue;
-  hipError_t e = set_lds_attr<R, GT, 0>();
+  hipError_t e = set_lds_attr<R, GT, 0, MODE>();
   if (e != hipSuccess) return e;
   const int n = ((a.W + kTW - 1) / kTW) * ((a.H + kTH - 1) / kTH);
   const int cus = cu_count_of_current_device();
   int grid = std::min(n, cus > 0 ? cus : 256);
   if (grid >= 8) grid -= grid % 8;               // whole XCD bands
-  hipLaunchKernelGGL((agg_wta_mfma_kernel<R, GT, 0>), dim3(grid), dim3(kThreads), MGeom<R>::lds_bytes, s,
+  hipLaunchKernelGGL((agg_wta_mfma_kernel<R, GT, 0, MODE>), dim3(grid), dim3(kThreads), MGeom<R>::lds_bytes, s,
                      view_of(a), (const BilPair*)nullptr, (const int*)nullptr, 0, (unsigned int*)nullptr);
   return hipGetLastError();
 }
@@ -481,19 +567,22 @@ hipError_t launch_pair(const BilPair& a, hipStream_t s) {
 template <int R, typename GT>
 hipError_t launch_queue(const BilPair* pairs, const int* tiles, int n_tiles, unsigned int* counter,
                         int n_groups, hipStream_t s) {
-  hipError_t e = set_lds_attr<R, GT, 1>();
+  hipError_t e = set_lds_attr<R, GT, 1, 1>();
   if (e != hipSuccess) return e;
   View none{};
-  hipLaunchKernelGGL((agg_wta_mfma_kernel<R, GT, 1>), dim3(n_groups), dim3(kThreads), MGeom<R>::lds_bytes, s,
+  hipLaunchKernelGGL((agg_wta_mfma_kernel<R, GT, 1, 1>), dim3(n_groups), dim3(kThreads), MGeom<R>::lds_bytes, s,
                      none, pairs, tiles, n_tiles, counter);
   return hipGetLastError();
 }
 
-// Entry points of one radius: the plan's pair (guide type from the args).
+// Entry points of one radius: the plan's pair (guide type from the args);
+// mode 1 selection, mode 2 soft-argmin.
 template <int R>
-hipError_t launch_args(const Plan& P, const BilArgs& a, hipStream_t s) {
+hipError_t launch_args(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
   const BilPair b = bil::make_pair(P, a);
-  return a.guide_dt == STEREO_U8 ? launch_pair<R, uint8_t>(b, s) : launch_pair<R, float>(b, s);
+  if (mode == 2)
+    return a.guide_dt == STEREO_U8 ? launch_pair<R, uint8_t, 2>(b, s) : launch_pair<R, float, 2>(b, s);
+  return a.guide_dt == STEREO_U8 ? launch_pair<R, uint8_t, 1>(b, s) : launch_pair<R, float, 1>(b, s);
 }
 
 template <int R>

@@ -3,7 +3,8 @@
 
 namespace stereo {
 hipError_t launch_bilateral_r3(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
-  if (mode == 1 && P.agg_engine == 1 && a.quad) return bilm::launch_args<3>(P, a, s);
+  if ((mode == 1 || mode == 2) && P.agg_engine == 1 && a.quad)
+    return bilm::launch_args<3>(P, a, mode, s);
   return bil::launch_r<3>(P, a, mode, s);
 }
 hipError_t launch_bilateral_persistent_r3(int engine, stereo_dtype gdt, int levels, const void* pairs,

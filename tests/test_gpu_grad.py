@@ -62,10 +62,13 @@ def case(name):
     return _cache[name]
 
 
+@pytest.mark.parametrize("engine", [1, 0])
 @pytest.mark.parametrize("name", list(CASES))
-def test_soft_forward(name):
+def test_soft_forward(name, engine):
+    """Both aggregation engines (1: matrix cores, 0: vector ALU)."""
     w, sc, g, fwd, bwd = case(name)
     plan = api.Plan.from_workload(w)
+    plan.set_tuning("agg_engine", engine)
     disp, saved = api.soft_forward(plan, _dev(sc.ref), _dev(sc.tar), w.plane)
     disp, saved = _host(disp), _host(saved)
     assert np.max(np.abs(disp - fwd["disp"]) / np.maximum(np.abs(fwd["disp"]), 1)) < 1e-4
@@ -174,3 +177,22 @@ def test_full_size_soft_forward_sampled():
         f.append(float(_host(d).mean()))
     fd = (f[0] - f[1]) / (2 * h)
     assert abs(gp[0] - fd) < 2e-2 * max(abs(fd), 1e-3), (gp[0], fd)
+
+
+def test_soft_engines_agree_at_full_size():
+    """1280x720 F32 pair, 48 levels, 11x11 aggregation: the matrix-core and the
+    vector-ALU engines sum in different orders; their soft levels and softmax
+    state agree to FP32 rounding at every pixel."""
+    w = workload("c5")
+    sc = make_workload_pair(w)
+    ref, tar = _dev(sc.ref), _dev(sc.tar)
+    out = []
+    for engine in (1, 0):
+        plan = api.Plan.from_workload(w)
+        plan.set_tuning("agg_engine", engine)
+        disp, saved = api.soft_forward(plan, ref, tar, w.plane)
+        out.append((_host(disp), _host(saved)))
+    (d1, s1), (d0, s0) = out
+    assert np.max(np.abs(d1 - d0) / np.maximum(np.abs(d0), 1)) < 2e-4
+    for k in range(3):
+        assert np.max(np.abs(s1[k] - s0[k]) / np.maximum(np.abs(s0[k]), 1)) < 2e-4, k
