@@ -132,8 +132,8 @@ stereo_status stereo_plan_set_homography(stereo_plan_t plan, const double* H);
  *   the vector-ALU aggregation kernel for 8-bit / float guides, 8 or 16
  *   (default 8); results are bitwise identical for every value;
  *   "ncc_levels": disparity levels per workgroup of the NCC cost kernel, 16,
- *   32 or 64, or 0 (default: 64, 32 or 16, the largest block the launch's
- *   levels fill); results are bitwise identical for every value;
+ *   32 or 64, or 0 (default: the smallest of 16, 32, 64 that holds the
+ *   launch's levels, else 64); results are bitwise identical for every value;
  *   "grad_levels": levels recomputed per tile by stereo_backward, a multiple
  *   of 4 in 4..64 (default 16); changes the workspace size and the FP32
  *   summation order of the gradients (not their value beyond rounding).

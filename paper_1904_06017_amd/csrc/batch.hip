@@ -164,11 +164,12 @@ void build_layout(stereo_batch_s& b) {
     push(Lt, i, 1, stats_job_blocks(P.W, P.H, P.r));
     Lt.r = std::max(Lt.r, P.r);
   }
-  // NCC: the largest level block every pair of the list fills, then the blocks
+  // NCC: the level block of the list's smallest pair (the smallest block that
+  // holds its levels, at most 64), then the blocks
   for (int i = 0; i < n; ++i) {
     const Plan& P = b.plans[i];
     JobList& L = list_of(JK_NCC, P.p.dtype, P.r);
-    const int dc = P.D >= 64 ? 64 : P.D >= 32 ? 32 : 16;
+    const int dc = P.D > 32 ? 64 : P.D > 16 ? 32 : 16;
     L.dc = L.pair.empty() ? dc : std::min(L.dc, dc);
     push(L, i, 0, 0);
   }

@@ -445,9 +445,12 @@ hipError_t launch_ncc_r(const Plan& P, const T* ref, const float* tar_w, const f
                         int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
                         int d_first, int d_end, int quad, hipStream_t s) {
   int dc = P.ncc_levels;
-  if (dc == 0) {                        // automatic: the largest block the levels fill
+  if (dc == 0) {
+    // automatic: the smallest block that holds every level, at most 64 (a
+    // larger block spreads the staging of the unshifted operand over more
+    // levels, which pays even when its last levels are idle)
     const int nl = d_end - d_first;
-    dc = nl >= 64 ? 64 : nl >= 32 ? 32 : 16;
+    dc = nl > 32 ? 64 : nl > 16 ? 32 : 16;
   }
   switch (dc) {
     case 32:
