@@ -135,8 +135,9 @@ stereo_status stereo_plan_set_homography(stereo_plan_t plan, const double* H);
  *   32 or 64, or 0 (default: the smallest of 16, 32, 64 that holds the
  *   launch's levels, else 64); results are bitwise identical for every value;
  *   "grad_levels": levels recomputed per tile by stereo_backward, a multiple
- *   of 4 in 4..64 (default 16); changes the workspace size and the FP32
- *   summation order of the gradients (not their value beyond rounding).
+ *   of 4 in 4..64 (default: num_disp rounded up to a multiple of 4, at most
+ *   64); changes the workspace size and the FP32 summation order of the
+ *   gradients (not their value beyond rounding).
  * Unknown keys and values give INVALID_ARGUMENT.  Not thread-safe against
  * concurrent enqueues on the same plan. */
 stereo_status stereo_plan_set_tuning(stereo_plan_t plan, const char* key, int32_t value);
@@ -342,7 +343,7 @@ stereo_status stereo_soft_forward(stereo_plan_t plan, const float* ref, const fl
 /* Vector-Jacobian product of disp_soft with grad_disp ([H][W] FP32): writes
  * grad_ref, grad_tar ([H][W] FP32) and grad_plane (device double[3]).  The cost
  * and aggregated volumes are recomputed per tile of "grad_levels" levels (a
- * tuning key, default 16).  Gradients flow through the aggregation weights
+ * tuning key; by default all levels up to 64 form one tile).  Gradients flow through the aggregation weights
  * (guide = ref), the NCC cost of both images, the warp and the shift back.
  * Deterministic: gathers in a fixed order, and fixed-point integer sums
  * (scale 2^44) where the warp scatters into the target image, so per-pixel

@@ -165,6 +165,9 @@ stereo_status stereo_plan_create(const stereo_params* params, stereo_plan_t* out
   P.D = params->num_disp;
   P.r = params->ncc_radius;
   P.R = params->bil_radius;
+  // backward tile: every level at once up to 64 (a few hundred MB of
+  // workspace at 1280x720); larger ranges are recomputed in 64-level tiles
+  P.grad_levels = std::min(64, (P.D + 3) / 4 * 4);
   layout(P);
   *out = pl;
   return STEREO_OK;

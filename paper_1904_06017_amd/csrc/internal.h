@@ -44,7 +44,7 @@ struct Plan {
   int agg_engine = 1;   // fused aggregation + selection: 1 matrix cores, 0 vector ALU
   // differentiable form (F32 plans): levels recomputed per backward tile and
   // the workspace regions it uses (offsets from the workspace base)
-  int grad_levels = 16;
+  int grad_levels = 16;  // set from D at plan creation
   size_t g_off[32];
   size_t g_end;
 };
@@ -59,6 +59,7 @@ enum GradRegion {
   GR_BS,                                        // [3][HV][WVX] boxes of the X sums
   GR_SY,                                        // [3][H][W+D-1] target-side sums
   GR_BSY,                                       // [3][HV][WVY] their boxes
+  GR_MU,                                        // [2][H][W+2r] block means of X, Y
   GR_GXV, GR_GYV, GR_GTARFIX, GR_PART_A, GR_PART_B, GR_SCRATCH, GR_COUNT
 };
 

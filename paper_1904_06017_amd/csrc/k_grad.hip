@@ -107,8 +107,8 @@ guide_finish_kernel(const GT* __restrict__ g, int64_t gpitch, const float* __res
 constexpr int CS_CH = 8, CS_HALO = 64;    // levels per chunk; halo >= nlev - 1
 __global__ void __launch_bounds__(kT)
 ncc_coef_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
-                const float* __restrict__ zX, const float* __restrict__ isdX,
-                const float* __restrict__ zY, const float* __restrict__ isdY, int W, int H,
+                const float* __restrict__ muX, const float* __restrict__ isdX,
+                const float* __restrict__ muY, const float* __restrict__ isdY, int W, int H,
                 int D, int r, int d_first, int nlev, float inv_n, float* __restrict__ Fa,
                 float* __restrict__ Sb, float* __restrict__ SbmX, float* __restrict__ SamY,
                 float* __restrict__ SaX, float* __restrict__ Sg, float* __restrict__ SgY) {
@@ -130,12 +130,12 @@ ncc_coef_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
   float iXo = 0.0f, mXo = 0.0f, iXh = 0.0f;
   if (own) {
     iXo = isdX[ro + xo + r];
-    mXo = iXo != 0.0f ? zX[ro + xo + r] / iXo : 0.0f;
+    mXo = muX[ro + xo + r];
     mx_s[tid] = mXo;
   }
   if (halo) {
     iXh = isdX[ro + xh + r];
-    mx_s[kT + tid] = iXh != 0.0f ? zX[ro + xh + r] / iXh : 0.0f;
+    mx_s[kT + tid] = muX[ro + xh + r];
   }
   const bool tgt = mi < WY;
   float iYm = 0.0f, mYm = 0.0f, sax = 0.0f, sg = 0.0f;
@@ -143,7 +143,7 @@ ncc_coef_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
   if (tgt) {
     const int cy = max(m, -r) + r;
     iYm = isdY[ro + cy];
-    mYm = iYm != 0.0f ? zY[ro + cy] / iYm : 0.0f;
+    mYm = muY[ro + cy];
     sax = SaX[q];
     sg = Sg[q];
   }
@@ -157,12 +157,13 @@ ncc_coef_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
   for (int tc = 0; tc < nlev; tc += CS_CH) {
     const int nc = min(CS_CH, nlev - tc);
     __syncthreads();                         // the previous chunk is consumed
+#pragma unroll 4
     for (int tt = 0; tt < nc; ++tt) {
       const int t = tc + tt, d = d_first + t;
       if (own) {
         const int cy = max(xo - d, -r) + r;
         const float iY = isdY[ro + cy];
-        const float mY = iY != 0.0f ? zY[ro + cy] / iY : 0.0f;
+        const float mY = muY[ro + cy];
         const bool flat = (iXo == 0.0f) || (iY == 0.0f);
         const float A = flat ? 0.0f : -gCt[t * HW + p] * inv_n;
         const float rho = 1.0f - Ct[t * HW + p];
@@ -471,6 +472,19 @@ zero_kernel(float* __restrict__ p, int64_t n) {
   if (i < n) p[i] = 0.0f;
 }
 
+// Block means mu = z / (1/sd) of both statistics maps (0 for flat blocks),
+// once per backward: the level loops of the NCC adjoint read them.
+__global__ void __launch_bounds__(256)
+mean_maps_kernel(const float* __restrict__ zX, const float* __restrict__ isdX,
+                 const float* __restrict__ zY, const float* __restrict__ isdY, int64_t n,
+                 float* __restrict__ muX, float* __restrict__ muY) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float iX = isdX[i], iY = isdY[i];
+  muX[i] = iX != 0.0f ? zX[i] / iX : 0.0f;
+  muY[i] = iY != 0.0f ? zY[i] / iY : 0.0f;
+}
+
 __global__ void __launch_bounds__(kT)
 zero_u64_kernel(unsigned long long* __restrict__ p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
@@ -551,6 +565,7 @@ size_t grad_layout(Plan& P, size_t o) {
   sz[GR_BS] = 3 * f4 * HV * WVX;
   sz[GR_SY] = 3 * f4 * (size_t)P.H * (P.W + P.D - 1);
   sz[GR_BSY] = 3 * f4 * HV * WVY;
+  sz[GR_MU] = 2 * f4 * (size_t)P.H * (P.W + 2 * P.r);
   sz[GR_GXV] = f4 * HV * WVX;
   sz[GR_GYV] = f4 * HV * WVY;
   sz[GR_GTARFIX] = sizeof(unsigned long long) * HW;
@@ -734,6 +749,13 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
   HIPC(launch_warp(P, tar, tarw, stream), "warp");
   HIPC(launch_block_stats(P, ref, STEREO_F32, P.p.pitch_ref, m.zX, m.isdX, stream), "stats");
   HIPC(launch_block_stats(P, tarw, STEREO_F32, W, m.zY, m.isdY, stream), "stats");
+  float* muX = R_(GR_MU);
+  float* muY = muX + (int64_t)H * (W + 2 * r);
+  {
+    const int64_t nmu = (int64_t)H * (W + 2 * r);
+    LAUNCH("block means", mean_maps_kernel, dim3((unsigned)((nmu + 255) / 256)), dim3(256), 0,
+           stream, m.zX, m.isdX, m.zY, m.isdY, nmu, muX, muY);
+  }
 
   const int n = (2 * r + 1) * (2 * r + 1);
   if (DT > CS_HALO) return fail(STEREO_ERR_INVALID_ARGUMENT, "grad_levels must be <= 64");
@@ -763,7 +785,7 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
     a.cpix = Ct;
     HIPC(launch_bilateral(P, a, 6, stream), "aggregation adjoint");
     LAUNCH("ncc adjoint coefficients", ncc_coef_kernel, dim3((WY + kT - 1) / kT, H), dim3(kT),
-           0, stream, Ct, gCt, m.zX, m.isdX, m.zY, m.isdY, W, H, D, r, d0, nl,
+           0, stream, Ct, gCt, muX, m.isdX, muY, m.isdY, W, H, D, r, d0, nl,
            1.0f / (float)n, Fa, Sb, SbmX, SamY, SaX, Sg, SgY);
     if ((st = box(P, W, Fa, nl, Ba, stream)) != STEREO_OK) return st;
     LAUNCH("ncc adjoint (reference side)", assemble_x_kernel, dim3((WVX + 255) / 256, HV),
