@@ -99,116 +99,80 @@ guide_finish_kernel(const GT* __restrict__ g, int64_t gpitch, const float* __res
 //   SaX(m) += sum_d alpha(m+d, d) muX(m+d),  Sg(m) += sum_d gamma(m+d, d),
 //   SgY(m) += sum_d gamma(m+d, d) muY(m),
 // maps [H][W + D - 1] at column index m + D - 1.
-// One pass serves both: the workgroup of target columns m0 .. m0 + 255 owns
-// the reference columns x0 = m0 + d_first .. x0 + 255 (their coefficients and
-// sums) and also forms alpha and A rho of the next nlev - 1 columns (the
-// diagonals of its m run into them).  Both are staged in LDS per chunk of
-// CS_CH levels, and every target sum then adds its diagonal in level order.
-constexpr int CS_CH = 8, CS_HALO = 64;    // levels per chunk; halo >= nlev - 1
+// Two passes per tile: the coefficients and reference-side sums by pixel,
+// then the target-side sums along the diagonals (the second pass re-reads C
+// and dC; one fused pass with the diagonals exchanged through LDS, or read
+// through the caches, measured slower).
 __global__ void __launch_bounds__(kT)
 ncc_coef_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
                 const float* __restrict__ muX, const float* __restrict__ isdX,
                 const float* __restrict__ muY, const float* __restrict__ isdY, int W, int H,
-                int D, int r, int d_first, int nlev, float inv_n, float* __restrict__ Fa,
-                float* __restrict__ Sb, float* __restrict__ SbmX, float* __restrict__ SamY,
-                float* __restrict__ SaX, float* __restrict__ Sg, float* __restrict__ SgY) {
-  __shared__ float al_s[CS_CH][kT + CS_HALO];
-  __shared__ float ar_s[CS_CH][kT + CS_HALO];
-  __shared__ float mx_s[kT + CS_HALO];
+                int r, int d_first, int nlev, float inv_n, float* __restrict__ Fa,
+                float* __restrict__ Sb, float* __restrict__ SbmX, float* __restrict__ SamY) {
+  const int x = blockIdx.x * kT + threadIdx.x, y = blockIdx.y;
+  if (x >= W) return;
+  const int64_t HW = (int64_t)W * H;
+  const int64_t p = (int64_t)y * W + x;
+  const int SW = W + 2 * r;
+  const int64_t ro = (int64_t)y * SW;
+  const float iX = isdX[ro + x + r];
+  const float mX = muX[ro + x + r];
+  float sb = Sb[p], sbm = SbmX[p], sam = SamY[p];
+#pragma unroll 4
+  for (int t = 0; t < nlev; ++t) {
+    const int d = d_first + t;
+    const int cy = max(x - d, -r) + r;
+    const float iY = isdY[ro + cy];
+    const float mY = muY[ro + cy];
+    const bool flat = (iX == 0.0f) || (iY == 0.0f);
+    const float A = flat ? 0.0f : -gCt[t * HW + p] * inv_n;
+    const float rho = 1.0f - Ct[t * HW + p];
+    const float al = A * iX * iY;
+    const float be = A * rho * iX * iX;
+    Fa[t * HW + p] = al;
+    sb += be;
+    sbm = fmaf(be, mX, sbm);
+    sam = fmaf(al, mY, sam);
+  }
+  Sb[p] = sb;
+  SbmX[p] = sbm;
+  SamY[p] = sam;
+}
+
+__global__ void __launch_bounds__(kT)
+ncc_shear_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
+                 const float* __restrict__ muX, const float* __restrict__ isdX,
+                 const float* __restrict__ muY, const float* __restrict__ isdY, int W, int H,
+                 int D, int r, int d_first, int nlev, float inv_n, float* __restrict__ SaX,
+                 float* __restrict__ Sg, float* __restrict__ SgY) {
   const int WY = W + D - 1;
-  const int tid = threadIdx.x, y = blockIdx.y;
-  const int mi = blockIdx.x * kT + tid;
+  const int mi = blockIdx.x * kT + threadIdx.x, y = blockIdx.y;
+  if (mi >= WY) return;
   const int m = mi - (D - 1);
-  const int x0 = blockIdx.x * kT - (D - 1) + d_first;
   const int64_t HW = (int64_t)W * H;
   const int SW = W + 2 * r;
   const int64_t ro = (int64_t)y * SW;
-  // own column (coefficients and sums) and halo column (target sums only)
-  const int xo = x0 + tid, xh = x0 + kT + tid;
-  const bool own = xo >= 0 && xo < W;
-  const bool halo = tid < nlev - 1 && xh >= 0 && xh < W;
-  float iXo = 0.0f, mXo = 0.0f, iXh = 0.0f;
-  if (own) {
-    iXo = isdX[ro + xo + r];
-    mXo = muX[ro + xo + r];
-    mx_s[tid] = mXo;
-  }
-  if (halo) {
-    iXh = isdX[ro + xh + r];
-    mx_s[kT + tid] = muX[ro + xh + r];
-  }
-  const bool tgt = mi < WY;
-  float iYm = 0.0f, mYm = 0.0f, sax = 0.0f, sg = 0.0f;
+  const int cy = max(m, -r) + r;
+  const float iY = isdY[ro + cy];
+  const float mY = muY[ro + cy];
   const int64_t q = (int64_t)y * WY + mi;
-  if (tgt) {
-    const int cy = max(m, -r) + r;
-    iYm = isdY[ro + cy];
-    mYm = muY[ro + cy];
-    sax = SaX[q];
-    sg = Sg[q];
-  }
-  const int64_t p = (int64_t)y * W + xo, ph = (int64_t)y * W + xh;
-  float sb = 0.0f, sbm = 0.0f, sam = 0.0f;
-  if (own) {
-    sb = Sb[p];
-    sbm = SbmX[p];
-    sam = SamY[p];
-  }
-  for (int tc = 0; tc < nlev; tc += CS_CH) {
-    const int nc = min(CS_CH, nlev - tc);
-    __syncthreads();                         // the previous chunk is consumed
+  float sax = SaX[q], sg = Sg[q];
 #pragma unroll 4
-    for (int tt = 0; tt < nc; ++tt) {
-      const int t = tc + tt, d = d_first + t;
-      if (own) {
-        const int cy = max(xo - d, -r) + r;
-        const float iY = isdY[ro + cy];
-        const float mY = muY[ro + cy];
-        const bool flat = (iXo == 0.0f) || (iY == 0.0f);
-        const float A = flat ? 0.0f : -gCt[t * HW + p] * inv_n;
-        const float rho = 1.0f - Ct[t * HW + p];
-        const float al = A * iXo * iY;
-        const float be = A * rho * iXo * iXo;
-        Fa[t * HW + p] = al;
-        sb += be;
-        sbm = fmaf(be, mXo, sbm);
-        sam = fmaf(al, mY, sam);
-        al_s[tt][tid] = al;
-        ar_s[tt][tid] = A * rho;
-      }
-      if (halo) {
-        const int cy = max(xh - d, -r) + r;
-        const float iY = isdY[ro + cy];
-        const bool flat = (iXh == 0.0f) || (iY == 0.0f);
-        const float A = flat ? 0.0f : -gCt[t * HW + ph] * inv_n;
-        const float rho = 1.0f - Ct[t * HW + ph];
-        al_s[tt][kT + tid] = A * iXh * iY;
-        ar_s[tt][kT + tid] = A * rho;
-      }
-    }
-    __syncthreads();
-    if (tgt) {
-      const float iY2 = iYm * iYm;
-      for (int tt = 0; tt < nc; ++tt) {
-        const int t = tc + tt;
-        const int x = m + d_first + t;
-        if (x < 0 || x >= W) continue;
-        const int u = tid + t;                 // x - x0
-        sax = fmaf(al_s[tt][u], mx_s[u], sax);
-        sg = fmaf(ar_s[tt][u], iY2, sg);
-      }
-    }
+  for (int t = 0; t < nlev; ++t) {
+    const int x = m + d_first + t;
+    if (x < 0 || x >= W) continue;
+    const float iX = isdX[ro + x + r];
+    const float mX = muX[ro + x + r];
+    const int64_t p = (int64_t)y * W + x;
+    const bool flat = (iX == 0.0f) || (iY == 0.0f);
+    const float A = flat ? 0.0f : -gCt[t * HW + p] * inv_n;
+    const float rho = 1.0f - Ct[t * HW + p];
+    sax = fmaf(A * iX * iY, mX, sax);
+    sg = fmaf(A * rho, iY * iY, sg);
   }
-  if (own) {
-    Sb[p] = sb;
-    SbmX[p] = sbm;
-    SamY[p] = sam;
-  }
-  if (tgt) {
-    SaX[q] = sax;
-    Sg[q] = sg;
-    SgY[q] = sg * mYm;
-  }
+  SaX[q] = sax;
+  Sg[q] = sg;
+  SgY[q] = sg * mY;
 }
 
 // Box sums onto a virtual domain: B(j) = sum_{o in [-r,r]^2} F(j - o) over
@@ -758,7 +722,6 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
   }
 
   const int n = (2 * r + 1) * (2 * r + 1);
-  if (DT > CS_HALO) return fail(STEREO_ERR_INVALID_ARGUMENT, "grad_levels must be <= 64");
   for (int d0 = 0; d0 < D; d0 += DT) {
     const int nl = std::min(DT, D - d0);
     // recompute this tile of the cost volume
@@ -784,9 +747,11 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
     a.E = gCt;
     a.cpix = Ct;
     HIPC(launch_bilateral(P, a, 6, stream), "aggregation adjoint");
-    LAUNCH("ncc adjoint coefficients", ncc_coef_kernel, dim3((WY + kT - 1) / kT, H), dim3(kT),
-           0, stream, Ct, gCt, muX, m.isdX, muY, m.isdY, W, H, D, r, d0, nl,
-           1.0f / (float)n, Fa, Sb, SbmX, SamY, SaX, Sg, SgY);
+    LAUNCH("ncc adjoint coefficients", ncc_coef_kernel, rows, dim3(kT), 0, stream, Ct, gCt,
+           muX, m.isdX, muY, m.isdY, W, H, r, d0, nl, 1.0f / (float)n, Fa, Sb, SbmX, SamY);
+    LAUNCH("ncc adjoint target sums", ncc_shear_kernel, dim3((WY + kT - 1) / kT, H), dim3(kT), 0,
+           stream, Ct, gCt, muX, m.isdX, muY, m.isdY, W, H, D, r, d0, nl, 1.0f / (float)n,
+           SaX, Sg, SgY);
     if ((st = box(P, W, Fa, nl, Ba, stream)) != STEREO_OK) return st;
     LAUNCH("ncc adjoint (reference side)", assemble_x_kernel, dim3((WVX + 255) / 256, HV),
            dim3(256), 0, stream, Ba, tarw, W, H, r, d0, nl, gXv);
