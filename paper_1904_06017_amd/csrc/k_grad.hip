@@ -157,18 +157,21 @@ ncc_shear_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
   const float mY = muY[ro + cy];
   const int64_t q = (int64_t)y * WY + mi;
   float sax = SaX[q], sg = Sg[q];
-#pragma unroll 4
+  // branch-free (clamped columns, results selected): the loads of several
+  // levels are in flight together
+#pragma unroll 8
   for (int t = 0; t < nlev; ++t) {
     const int x = m + d_first + t;
-    if (x < 0 || x >= W) continue;
-    const float iX = isdX[ro + x + r];
-    const float mX = muX[ro + x + r];
-    const int64_t p = (int64_t)y * W + x;
+    const bool ok = x >= 0 && x < W;
+    const int xc = min(max(x, 0), W - 1);
+    const float iX = isdX[ro + xc + r];
+    const float mX = muX[ro + xc + r];
+    const int64_t p = (int64_t)y * W + xc;
     const bool flat = (iX == 0.0f) || (iY == 0.0f);
     const float A = flat ? 0.0f : -gCt[t * HW + p] * inv_n;
     const float rho = 1.0f - Ct[t * HW + p];
-    sax = fmaf(A * iX * iY, mX, sax);
-    sg = fmaf(A * rho, iY * iY, sg);
+    sax = ok ? fmaf(A * iX * iY, mX, sax) : sax;
+    sg = ok ? fmaf(A * rho, iY * iY, sg) : sg;
   }
   SaX[q] = sax;
   Sg[q] = sg;
