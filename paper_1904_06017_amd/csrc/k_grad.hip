@@ -433,10 +433,18 @@ fix_to_float_kernel(const unsigned long long* __restrict__ fx, int64_t n, const 
   out[i] = (float)v + (add ? add[i] : 0.0f);
 }
 
+// Several regions cleared by one launch: grid.y picks the region.
+constexpr int kZeroMax = 8;
+struct ZeroList {
+  float* p[kZeroMax];
+  int64_t n[kZeroMax];
+};
+
 __global__ void __launch_bounds__(kT)
-zero_kernel(float* __restrict__ p, int64_t n) {
+zero_many_kernel(ZeroList z) {
+  const int k = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
-  if (i < n) p[i] = 0.0f;
+  if (i < z.n[k]) z.p[k][i] = 0.0f;
 }
 
 // Block means mu = z / (1/sd) of both statistics maps (0 for flat blocks),
@@ -596,11 +604,6 @@ Maps maps_of(const Plan& P, void* ws) {
   return {b, b + n, b + 2 * n, b + 3 * n};
 }
 
-stereo_status zero_f(float* p, int64_t n, hipStream_t s) {
-  LAUNCH("zero", zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
-  return STEREO_OK;
-}
-
 template <int r>
 stereo_status box_r(int W, int H, const float* F, int nmaps, float* B, hipStream_t s) {
   dim3 grid((W + 2 * r + BX_TX - 1) / BX_TX, (H + 2 * r + BX_TY - 1) / BX_TY, nmaps);
@@ -702,15 +705,23 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
   const dim3 flat((unsigned)((HW + 255) / 256));
   const int nb = (int)rows.x * H;
 
-  // accumulators (cleared by kernels: graph-safe)
-  for (float* z : {aP, A1, A2, SamY, Sb, SbmX}) {
-    st = zero_f(z, HW, stream);
-    if (st != STEREO_OK) return st;
+  // accumulators, cleared by one kernel launch (graph-safe; the fixed-point
+  // target accumulator is cleared as two floats per element, all bits zero)
+  {
+    ZeroList z{};
+    float* const reg[kZeroMax] = {aP, A1, A2, SamY, SaX, gXv, gYv,
+                                  reinterpret_cast<float*>(gfix)};
+    const int64_t len[kZeroMax] = {HW, HW, HW, 3 * HW, 2 * HWY, HVWV, (int64_t)HV * WVY,
+                                   2 * HW};
+    int64_t nmax = 0;
+    for (int k = 0; k < kZeroMax; ++k) {
+      z.p[k] = reg[k];
+      z.n[k] = len[k];
+      nmax = std::max(nmax, len[k]);
+    }
+    LAUNCH("zero", zero_many_kernel, dim3((unsigned)((nmax + kT - 1) / kT), kZeroMax), dim3(kT),
+           0, stream, z);
   }
-  if ((st = zero_f(SaX, 2 * HWY, stream)) != STEREO_OK) return st;
-  if ((st = zero_f(gXv, HVWV, stream)) != STEREO_OK) return st;
-  if ((st = zero_f(gYv, (int64_t)HV * WVY, stream)) != STEREO_OK) return st;
-  LAUNCH("zero", zero_u64_kernel, flat, dim3(256), 0, stream, gfix, HW);
 
   // forward state that is cheap to rebuild: warp, block statistics
   HIPC(launch_warp(P, tar, tarw, stream), "warp");
