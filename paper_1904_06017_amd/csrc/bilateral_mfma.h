@@ -456,36 +456,41 @@ agg_wta_mfma_kernel(View one, const BilPair* __restrict__ pairs, const int* __re
         }
         lastE = prow[D - d0 < 16 ? D - d0 - 1 : 15];
       } else {
-        // soft-argmin over the pass: per lane over its four levels, then the
-        // quad and the running state by max-rescaled sums
+        // soft-argmin: each lane keeps the running state of its quarter of
+        // every pass's levels (rescaled when its maximum grows); the quad is
+        // merged once per tile, below
         const float4 e4 = *reinterpret_cast<const float4*>(prow + 4 * Q);
         const int nvl = D - d0 - 4 * Q;
         const float zv[4] = {nvl > 0 ? e4.x * rinvP * zscale : kNeg, nvl > 1 ? e4.y * rinvP * zscale : kNeg,
                              nvl > 2 ? e4.z * rinvP * zscale : kNeg, nvl > 3 ? e4.w * rinvP * zscale : kNeg};
-        float m = fmaxf(fmaxf(zv[0], zv[1]), fmaxf(zv[2], zv[3]));
-        float Zl = 0.0f, Sl = 0.0f;
+        const float M = fmaxf(mr, fmaxf(fmaxf(zv[0], zv[1]), fmaxf(zv[2], zv[3])));
+        const float a = __builtin_amdgcn_exp2f(mr - M);
+        Zr *= a;
+        Sr *= a;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const float e = nvl > j ? __builtin_amdgcn_exp2f(zv[j] - m) : 0.0f;
-          Zl += e;
-          Sl = fmaf((float)(d0 + 4 * Q + j), e, Sl);
+          const float e = nvl > j ? __builtin_amdgcn_exp2f(zv[j] - M) : 0.0f;
+          Zr += e;
+          Sr = fmaf((float)(d0 + 4 * Q + j), e, Sr);
         }
-        auto merge = [&](float om, float oZ, float oS) {
-          const float M = fmaxf(m, om);
-          const float a = __builtin_amdgcn_exp2f(m - M), b = __builtin_amdgcn_exp2f(om - M);
-          Zl = fmaf(Zl, a, oZ * b);
-          Sl = fmaf(Sl, a, oS * b);
-          m = M;
-        };
-        merge(dpp_f<0xB1>(m), dpp_f<0xB1>(Zl), dpp_f<0xB1>(Sl));
-        merge(dpp_f<0x4E>(m), dpp_f<0x4E>(Zl), dpp_f<0x4E>(Sl));
-        merge(mr, Zr, Sr);
-        mr = m; Zr = Zl; Sr = Sl;
+        mr = M;
       }
       if (last && has_next) guide_store<R>(gpar ? gbuf0 : gbuf1, gq);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
       par ^= 1;
+    }
+    if constexpr (MODE == 2) {
+      // the quad's four running states into one (every lane takes part)
+      auto merge = [&](float om, float oZ, float oS) {
+        const float M = fmaxf(mr, om);
+        const float a = __builtin_amdgcn_exp2f(mr - M), b = __builtin_amdgcn_exp2f(om - M);
+        Zr = fmaf(Zr, a, oZ * b);
+        Sr = fmaf(Sr, a, oS * b);
+        mr = M;
+      };
+      merge(dpp_f<0xB1>(mr), dpp_f<0xB1>(Zr), dpp_f<0xB1>(Sr));
+      merge(dpp_f<0x4E>(mr), dpp_f<0x4E>(Zr), dpp_f<0x4E>(Sr));
     }
     if (MODE == 2 && Q == 0) {
       // soft level, the saved state (m, log Z) in natural units, and the
