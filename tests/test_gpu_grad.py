@@ -96,15 +96,20 @@ def test_backward_is_deterministic_and_tile_invariant():
     w, sc, g, fwd, bwd = case("c5_crop")
     ref, tar = _dev(sc.ref), _dev(sc.tar)
     res = []
-    for lv in (16, 16, 8):
+    for lv in (16, 16, 8, None):
         plan = api.Plan.from_workload(w)
-        plan.set_tuning("grad_levels", lv)
+        if lv is None:
+            # the default: every level (45, rounded up to 48) in one tile
+            assert plan.get_tuning("grad_levels") == 48
+        else:
+            plan.set_tuning("grad_levels", lv)
         disp, saved = api.soft_forward(plan, ref, tar, w.plane)
         res.append([_host(x) for x in api.backward(plan, ref, tar, w.plane, saved, _dev(g))])
     for a, b in zip(res[0], res[1]):
         assert np.array_equal(a, b)          # same tiling: bitwise
-    for a, b in zip(res[0], res[2]):
-        assert _rel_l2(a, b) < 1e-5          # another tiling: rounding only
+    for other in (res[2], res[3]):
+        for a, b in zip(res[0], other):
+            assert _rel_l2(a, b) < 1e-5      # another tiling: rounding only
 
 
 @pytest.mark.parametrize("name", list(CASES))
