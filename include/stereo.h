@@ -226,6 +226,23 @@ stereo_status stereo_road_transform(stereo_plan_t plan, const float* disp,
                                     void* ws, size_t ws_bytes,
                                     hipStream_t stream);
 
+/* ---- the road transform without a workspace -------------------------------
+ * For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): stereo_road_transform
+ * with its reduction partials (10 FP64 per reduction block, 240 blocks,
+ * 19200 bytes) in a fixed device buffer of 80 KiB that the library holds on
+ * every device it runs on until the process ends.  Allocates nothing and
+ * never synchronises; same arguments, semantics and bitwise results as
+ * stereo_road_transform.  Returns UNSUPPORTED if the plan's partials exceed
+ * the buffer.  Calls that overlap on one device (several streams or host
+ * threads at once) share the buffer and race: serialise them. */
+stereo_status stereo_road_transform_noalloc(stereo_plan_t plan, const float* disp,
+                                            const uint8_t* mask, double psi_init,
+                                            double lambda0, double delta_psi,
+                                            int32_t max_iter, float delta_t,
+                                            stereo_road_fit* fit_dev, float* disp_t,
+                                            hipStream_t stream);
+
 /* ---- closed-loop plane tracking over a frame sequence ----------------------
  * The road fit of frame t (Sec. 3.3) gives the plane c = (alpha0,
  * -alpha1 sin psi, alpha1 cos psi) that frame t+1's perspective

@@ -86,6 +86,9 @@ SIGNATURES = {
     "stereo_road_transform": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double,
                                       c_double, c_int32, c_float, c_void_p, c_void_p,
                                       c_void_p, c_size_t, c_void_p]),
+    "stereo_road_transform_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_double,
+                                              c_double, c_double, c_int32, c_float, c_void_p,
+                                              c_void_p, c_void_p]),
     "stereo_match_tracked": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                      c_void_p]),

@@ -251,6 +251,26 @@ def road_transform(plan: Plan, disp, mask=None, psi_init=0.0, lambda0=LAMBDA0,
     return (road_fit_from_bytes(fit_buf) if read_fit else fit_buf), out
 
 
+def road_transform_noalloc(plan: Plan, disp, mask=None, psi_init=0.0, lambda0=LAMBDA0,
+                           delta_psi=DELTA_PSI, max_iter=100, delta_t=0.0, fit_buf=None,
+                           out=None, read_fit=True):
+    """road_transform through the entry point that uses the library's fixed
+    device buffer instead of the plan's workspace (allocates nothing on the
+    device when fit_buf and out are given)."""
+    _need(disp, torch.float32, (plan.H, plan.W), "disp")
+    if mask is not None:
+        _need(mask, torch.uint8, (plan.H, plan.W), "mask")
+    dev = disp.device
+    if fit_buf is None:
+        fit_buf = torch.empty(ctypes.sizeof(RoadFit), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = torch.empty_like(disp)
+    check(_lib.load().stereo_road_transform_noalloc(
+        plan.handle, _p(disp), _p(mask), float(psi_init), float(lambda0), float(delta_psi),
+        int(max_iter), float(delta_t), _p(fit_buf), _p(out), _stream()))
+    return (road_fit_from_bytes(fit_buf) if read_fit else fit_buf), out
+
+
 class PlaneTracker:
     """Closed-loop plane estimation over a frame sequence: each frame is
     matched with the plane fitted on the previous one (state in device

@@ -442,6 +442,32 @@ stereo_status stereo_road_transform(stereo_plan_t plan, const float* disp,
   return STEREO_OK;
 }
 
+stereo_status stereo_road_transform_noalloc(stereo_plan_t plan, const float* disp,
+                                            const uint8_t* mask, double psi_init,
+                                            double lambda0, double delta_psi,
+                                            int32_t max_iter, float delta_t,
+                                            stereo_road_fit* fit_dev, float* disp_t,
+                                            hipStream_t stream) {
+  STEREO_REQUIRE(plan && disp && fit_dev, "plan, disp and fit_dev must be non-NULL");
+  STEREO_REQUIRE(max_iter >= 1, "max_iter must be >= 1");
+  STEREO_REQUIRE(lambda0 > 0.0 && std::isfinite(lambda0), "lambda0 must be finite and > 0");
+  STEREO_REQUIRE(delta_psi > 0.0, "delta_psi must be > 0");
+  STEREO_REQUIRE(std::isfinite(psi_init), "psi_init must be finite");
+  const Plan& P = plan->P;
+  double* partials = nullptr;
+  size_t cap = 0;
+  STEREO_HIP(road_scratch(&partials, &cap), "road transform (fixed buffer address)");
+  const size_t need = sizeof(double) * 10 * (size_t)P.road_blocks;
+  if (need > cap)
+    return fail(STEREO_ERR_UNSUPPORTED,
+                "road transform needs %zu bytes of partials, the fixed buffer holds %zu", need,
+                cap);
+  STEREO_HIP(launch_road(P, disp, mask, psi_init, lambda0, delta_psi, max_iter, delta_t,
+                         fit_dev, disp_t, partials, stream),
+             "road transform (fixed buffer)");
+  return STEREO_OK;
+}
+
 stereo_status stereo_road_transform_tracked(stereo_plan_t plan, const float* disp,
                                             const uint8_t* mask, double lambda0,
                                             double delta_psi, int32_t max_iter,

@@ -217,6 +217,12 @@ size_t grad_layout(Plan& P, size_t base);
 hipError_t launch_damage_mask(const Plan& P, const float* disp_t, float delta_t, float tau,
                               uint8_t* mask, hipStream_t s);
 
+// Device address and size of this device's fixed road-transform buffer
+// (allocation-free entry point); looked up once per device.
+constexpr int kMaxDevices = 64;
+constexpr int kRoadScratchDoubles = 10 * 1024;
+hipError_t road_scratch(double** out, size_t* bytes);
+
 hipError_t launch_road(const Plan& P, const float* disp, const uint8_t* mask,
                        double psi0, double lambda0, double delta_psi,
                        int max_iter, float delta_t, stereo_road_fit* fit,

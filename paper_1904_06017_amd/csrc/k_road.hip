@@ -12,6 +12,8 @@
 // The sums are accumulated in FP64 in a fixed order (per-thread grid-stride
 // sums, a fixed tree per block, then a fixed tree over the block partials),
 // so the fit is deterministic.
+#include <mutex>
+
 #include "internal.h"
 
 namespace stereo {
@@ -235,6 +237,33 @@ hipError_t launch_damage_mask(const Plan& P, const float* disp_t, float delta_t,
   hipLaunchKernelGGL(damage_mask_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                      disp_t, n, level, mask);
   return hipGetLastError();
+}
+
+// Fixed device buffer of the allocation-free road transform: room for the
+// ten FP64 moment partials of up to kRoadScratchDoubles / 10 reduction
+// blocks.  Every device the library runs on holds one copy for the life of
+// the process; calls on one device share it.
+static __device__ __align__(256) double scratch[kRoadScratchDoubles];
+
+hipError_t road_scratch(double** out, size_t* bytes) {
+  static std::mutex mu;
+  static double* ptr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    // the array's name is a host-side stand-in: the device address of this
+    // device's copy comes from the runtime, once per device
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptr[dev] = static_cast<double*>(p);
+  }
+  *out = ptr[dev];
+  *bytes = sizeof(double) * (size_t)kRoadScratchDoubles;
+  return hipSuccess;
 }
 
 hipError_t launch_road(const Plan& P, const float* disp, const uint8_t* mask,
