@@ -54,6 +54,34 @@ def _make(pairs):
     return items
 
 
+@pytest.mark.timeout(900)
+def test_full_batch_equals_plain_path():
+    """The whole 64-pair batch (16 x 320x240, 24 x 640x480, 16 x 1280x720,
+    8 x 1920x1080; 32-96 levels per pair) in the benchmark's launch
+    configuration: every pair bitwise equal to its plain per-pair match."""
+    import time
+
+    from synth import make_workload_pair as gen
+    from tests import oracle_bands as OB
+    ws = batch_workloads()
+    t = time.time()
+    with OB.process_pool() as pool:
+        scenes = list(pool.map(gen, ws))
+    print(f"[batch] generated {len(ws)} pairs in {time.time() - t:.1f} s", flush=True)
+    items = [(api.Plan.from_workload(w), torch.from_numpy(sc.ref).cuda(),
+              torch.from_numpy(sc.tar).cuda()) for w, sc in zip(ws, scenes)]
+    b = api.Batch(items)
+    outs = b.submit()
+    torch.cuda.synchronize()
+    for i, ((plan, ref, tar), o) in enumerate(zip(items, outs)):
+        m = api.match(plan, ref, tar)
+        for k in ("dint_R", "valid", "disp"):
+            assert np.array_equal(_host(m[k]), _host(o[k]), equal_nan=True), (i, k, ws[i].name)
+        plan._ws = None                      # release the per-pair workspace
+        del m
+    print(f"[batch] {len(items)} pairs bitwise equal to the plain path", flush=True)
+
+
 @pytest.mark.parametrize("engine", [1, 0], ids=["mfma", "valu"])
 def test_batch_equals_plain_path(small_batch, engine):
     items = _make(small_batch)

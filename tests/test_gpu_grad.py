@@ -4,6 +4,8 @@ Bars: soft disparity and softmax state within 1e-4 * max(|x|, 1); every
 gradient tensor within a relative L2 error of 1e-3, the three plane
 components each within 1e-3 relative.
 """
+from dataclasses import replace
+
 import numpy as np
 import pytest
 import torch
@@ -42,7 +44,12 @@ CASES = {
     "rolled": dict(w=(130, 70), D=28, dp=14.0, plane=(14.3, -0.02, 0.09), R=4, r=2, seed=52),
     # the compiled maximum radii
     "max_radii": dict(w=(80, 40), D=20, dp=10.0, plane=(14.0, 0.01, 0.09), R=8, r=8, seed=55),
+    # an exactly uniform reference patch (zero-variance blocks: cost 1, no
+    # NCC gradient) and a uniform target strip along the bottom border
+    "flat": dict(w=(120, 64), D=24, dp=12.0, plane=(14.3, 0.0, 0.1), R=4, r=2, seed=56,
+                 flat_ref=(14, 44, 40, 80), flat_tar=(54, 64, 0, 120)),
 }
+FLAT_VALUE = 131.0
 _cache = {}
 
 
@@ -53,6 +60,13 @@ def case(name):
         w = crop_workload(workload("c5"), W, H, num_disp=c["D"], delta_p=c["dp"],
                           plane=c["plane"], bil_radius=c["R"], ncc_radius=c["r"])
         sc = make_scene(W, H, c["plane"], 2, 1, c["seed"], float_images=True)
+        if "flat_ref" in c:
+            ref, tar = sc.ref.copy(), sc.tar.copy()
+            y0, y1, x0, x1 = c["flat_ref"]
+            ref[y0:y1, x0:x1] = FLAT_VALUE
+            y0, y1, x0, x1 = c["flat_tar"]
+            tar[y0:y1, x0:x1] = FLAT_VALUE
+            sc = replace(sc, ref=ref, tar=tar)
         rng = np.random.default_rng(c["seed"])
         g = ndimage.gaussian_filter(rng.normal(size=(H, W)), 2.0).astype(np.float32)
         print(f"[grad] case {name}: {W}x{H} D={c['D']} R={c['R']} r={c['r']}", flush=True)
@@ -90,6 +104,25 @@ def test_backward_matches_fp64_adjoint(name):
     gp = _host(g_plane)
     for k in range(3):
         assert abs(gp[k] - o_plane[k]) <= 1e-3 * max(abs(o_plane[k]), 1e-6 * np.abs(o_plane).max()), (k, gp, o_plane)
+
+
+def test_flat_patch_has_no_ncc_gradient():
+    """Inside an exactly uniform reference patch, deeper than 2r (every block
+    reading the pixel is uniform: cost 1, no NCC gradient) and deeper than R
+    (every guide difference is zero: no range-weight gradient), the
+    reference gradient is exactly zero, on the GPU as in the oracle."""
+    w, sc, g, fwd, bwd = case("flat")
+    c = CASES["flat"]
+    plan = api.Plan.from_workload(w)
+    ref, tar = _dev(sc.ref), _dev(sc.tar)
+    disp, saved = api.soft_forward(plan, ref, tar, w.plane)
+    g_ref, _, _ = api.backward(plan, ref, tar, w.plane, saved, _dev(g))
+    y0, y1, x0, x1 = c["flat_ref"]
+    m = max(c["R"], 2 * c["r"]) + 1
+    inner = (slice(y0 + m, y1 - m), slice(x0 + m, x1 - m))
+    assert np.all(bwd[0][inner] == 0.0)
+    assert np.all(_host(g_ref)[inner] == 0.0)
+    assert np.any(bwd[0][y0:y1, x0:x1] != 0.0)     # the patch rim still has gradient
 
 
 def test_backward_is_deterministic_and_tile_invariant():

@@ -138,3 +138,45 @@ def test_soft_forward_reuses_the_plain_pipeline():
     plain = OS.match(sc.ref, sc.tar, w, keep_volumes=True)
     assert np.array_equal(fwd["E"], plain["E_R"])
     assert np.allclose(fwd["P"].sum(0), 1.0)
+
+
+def test_softmax_state_closed_form_on_uniform_costs():
+    """A uniform reference has zero-variance blocks everywhere, so every cost
+    is 1 (Eq. 8 undefined, read as 1) and so is every aggregated cost: the
+    soft-argmin is then uniform over the D levels, with max_d(-E/T) = -1/T,
+    log Z = ln D (Z = sum_d exp(-E/T - max)) and soft level (D - 1) / 2."""
+    w = crop_workload(workload("c5"), 37, 23, num_disp=11, delta_p=5.0, bil_radius=2,
+                      ncc_radius=1, plane=(5.3, 0.0, 0.1))
+    sc = make_scene(37, 23, (5.3, 0.0, 0.1), 0, 0, 71, float_images=True)
+    ref = np.full((23, 37), 97.25)
+    f = SO.soft_forward(ref, sc.tar, w.plane, w, T=0.25)
+    assert np.all(f["C"] == 1.0)
+    assert np.allclose(f["E"], 1.0, rtol=0, atol=1e-14)
+    assert np.allclose(f["m"], -1.0 / 0.25, rtol=0, atol=1e-12)
+    assert np.allclose(f["logZ"], np.log(11.0), rtol=0, atol=1e-12)
+    assert np.allclose(f["P"], 1.0 / 11.0, rtol=0, atol=1e-14)
+    assert np.allclose(f["dh"], 5.0, rtol=0, atol=1e-12)
+
+
+def test_softmax_state_is_the_log_partition_function():
+    """On a textured pair: m is the maximum of -E/T over levels and m + log Z
+    is log sum_d exp(-E/T), computed by scipy's logsumexp (its own
+    max-shifted evaluation); P sums to one; the soft level lies in [0, D-1]."""
+    from scipy.special import logsumexp
+    w = crop_workload(workload("c5"), 41, 29, num_disp=13, delta_p=6.0, bil_radius=2,
+                      ncc_radius=1, plane=(6.2, 0.0, 0.1))
+    sc = make_scene(41, 29, (6.2, 0.0, 0.1), 1, 0, 72, float_images=True)
+    T = 0.1
+    f = SO.soft_forward(sc.ref, sc.tar, w.plane, w, T=T)
+    z = -f["E"] / T
+    assert np.array_equal(f["m"], z.max(axis=0))
+    assert np.allclose(f["m"] + f["logZ"], logsumexp(z, axis=0), rtol=0, atol=1e-12)
+    assert np.allclose(f["P"].sum(axis=0), 1.0, rtol=0, atol=1e-13)
+    assert np.all((f["dh"] >= 0) & (f["dh"] <= 12))
+    # a two-level closed form: P(d=1) = 1 / (1 + exp((E1 - E0) / T))
+    two = crop_workload(w, 41, 29, num_disp=2, delta_p=1.0)
+    f2 = SO.soft_forward(sc.ref, sc.tar, w.plane, two, T=T)
+    p1 = 1.0 / (1.0 + np.exp((f2["E"][1] - f2["E"][0]) / T))
+    assert np.allclose(f2["dh"], p1, rtol=0, atol=1e-13)
+    assert np.allclose(f2["logZ"], np.log1p(np.exp(-np.abs(f2["E"][1] - f2["E"][0]) / T)),
+                       rtol=0, atol=1e-13)
