@@ -30,6 +30,31 @@ MI355X_FP32_PACKED_TFLOPS = 157.3
 # dense FP32 matrix-core rate: v_mfma_f32_16x16x4f32 is 16*16*4 FMAs per SIMD
 # every 32 cycles, 256 CUs x 4 SIMDs x 2.4 GHz
 MI355X_FP32_MFMA_TFLOPS = 157.3
+# dense FP16 matrix-core rate (v_mfma_f32_16x16x32_f16), published
+MI355X_FP16_MFMA_TFLOPS = 2500.0
+
+
+def mfma16_k(R):
+    """Union positions one pixel-level of the split-FP16 aggregation multiplies:
+    a 4x4 pixel block's (4 + 2R)-row window union, cut in 2-row x 4-column
+    patches (columns rounded up to whole quads), four patches per product."""
+    n_patch = (R + 2) * (((4 + 2 * R + 3) & ~3) // 4)
+    return ((n_patch + 3) // 4) * 32
+
+
+def host_cpu():
+    """Logical CPUs visible to this process and the CPU model name."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return n, model
 
 
 def _sha(path):
@@ -59,8 +84,9 @@ def cpu_baseline(w, sc, rows):
         t0 = time.perf_counter()
         OS.match(sc.ref[:rows], sc.tar[:rows], ws)
         dt = time.perf_counter() - t0
+    nproc, model = host_cpu()
     return dict(value=w.width * rows * w.num_disp / dt / 1e9, unit="G pixel·disparities/s",
-                cores=1, kind="oracle", seconds=round(dt, 2),
+                cores=1, kind="oracle", seconds=round(dt, 2), host_nproc=nproc, host_cpu=model,
                 sample=f"rows 0..{rows - 1} of the {w.width}x{w.height} pair, D={w.num_disp}, "
                        f"full plain path (FP64 numpy, single thread)")
 
@@ -71,19 +97,33 @@ def _gen(w):
     return sc.ref, sc.tar
 
 
-def batch_scenes():
-    """The 64 seeded pairs of the mixed batch and the tracking sequence,
-    generated on host cores (a process pool started before the GPU is
-    touched)."""
+def batch_scenes(serial=False):
+    """The 64 seeded pairs of the mixed batch, the tracking sequence and the
+    skewed rig, generated on host cores: by a pool of fresh ("spawn") worker
+    processes that import numpy and the generator only, closed and joined
+    when done, or in this process (serial=True, for runs under a profiler,
+    which would follow every worker)."""
     import multiprocessing as mp
     from synth import batch_workloads
     ws = batch_workloads()
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+    if serial:
+        imgs = []
+        for i, w in enumerate(ws):
+            imgs.append(_gen(w))
+            if i % 16 == 15:
+                print(f"[bench] generated {i + 1}/{len(ws)} batch pairs", file=sys.stderr,
+                      flush=True)
+        return (ws, imgs), (sequence_frames(), skewed_frames())
+    pool = mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1))
+    try:
         seq = pool.apply_async(sequence_frames)
         sk = pool.apply_async(skewed_frames)
         imgs = pool.map(_gen, ws)
         seq = seq.get()
         sk = sk.get()
+    finally:
+        pool.close()
+        pool.join()
     return (ws, imgs), (seq, sk)
 
 
@@ -247,7 +287,7 @@ def batched(args, scenes):
 
 
 def run(args):
-    scenes, (seq, sk) = batch_scenes() if args.extra else (None, (None, None))
+    scenes, (seq, sk) = batch_scenes(args.serial_inputs) if args.extra else (None, (None, None))
     import torch
 
     from paper_1904_06017_amd import api
@@ -316,7 +356,23 @@ def run(args):
     agg_s = (st["aggregate_wta_ref_ms"] + st["aggregate_wta_tar_ms"]) / 2.0 / 1e3
     achieved = flops_per_launch / agg_s / 1e12
     engine = plan.get_tuning("agg_engine")
-    if engine == 1:
+    if engine == 2:
+        # matrix cores with split-FP16 operands: each 4x4 pixel block multiplies
+        # over its patch-padded window union (mfma16_k positions per
+        # pixel-level) and every product is three FP16 MFMAs (hi.hi, hi.lo,
+        # lo.hi), so the issued FP16 flops are 3 x 2 x mfma16_k per element
+        src = os.path.join(ROOT, "paper_1904_06017_amd", "csrc", "bilateral_mfma16.h")
+        issued = 3 * 2.0 * mfma16_k(w.bil_radius) * elements
+        roof = dict(kernel="agg_mfma16_kernel (aggregation + fused WTA, both volumes)",
+                    bound="mfma", achieved=round(achieved, 2), peak=MI355X_FP16_MFMA_TFLOPS,
+                    unit="TFLOP/s", frac=round(achieved / MI355X_FP16_MFMA_TFLOPS, 4),
+                    issued_tflops=round(issued / agg_s / 1e12, 1),
+                    issued_frac=round(issued / agg_s / 1e12 / MI355X_FP16_MFMA_TFLOPS, 4),
+                    frac_vs_fp32_peak=round(achieved / MI355X_FP32_MFMA_TFLOPS, 4),
+                    flops_per_launch=flops_per_launch, issued_flops_per_launch=issued,
+                    avg_launch_ms=round(agg_s * 1e3, 4),
+                    traffic=_traffic(src, "hbm_bytes_per_launch"))
+    elif engine == 1:
         # matrix cores: each 4x4 pixel block multiplies over its (2R + 4)^2
         # window union, (2R + 4)^2 / (2R + 1)^2 of the algorithmic products
         src = os.path.join(ROOT, "paper_1904_06017_amd", "csrc", "bilateral_mfma.h")
@@ -335,12 +391,19 @@ def run(args):
                     frac_of_packed_peak=round(achieved / MI355X_FP32_PACKED_TFLOPS, 4),
                     flops_per_launch=flops_per_launch, avg_launch_ms=round(agg_s * 1e3, 4),
                     traffic=_traffic(src, "hbm_bytes_per_launch"))
-    # NCC stage: HBM-bound when the volume is materialised
-    cw = ((W + w.num_disp - 1) + 3) & ~3
-    ncc_bytes = 4.0 * w.num_disp * H * (W + w.num_disp - 1)
+    # NCC stage: HBM-bound when the volume is materialised.  Engines 0 and 1
+    # write one FP32 reference-anchored volume over the extended columns
+    # (the target volume is its re-indexing); engine 2 writes the two
+    # anchored volumes, each element as two FP16 halves.
+    if engine == 2:
+        ncc_bytes = 2 * 4.0 * w.num_disp * H * W
+        ncc_kernel = "ncc_kernel (split-FP16 output, both anchors)"
+    else:
+        ncc_bytes = 4.0 * w.num_disp * H * (W + w.num_disp - 1)
+        ncc_kernel = "ncc_kernel (FP32 quad output)"
     ncc_gbs = ncc_bytes / (st["ncc_ms"] / 1e3) / 1e9
     hbm = achievable_hbm(int(ncc_bytes))
-    ncc = dict(kernel="ncc_kernel", bound="hbm", achieved=round(ncc_gbs, 1),
+    ncc = dict(kernel=ncc_kernel, bound="hbm", achieved=round(ncc_gbs, 1),
                peak=MI355X_HBM_GBS, unit="GB/s",
                frac=round(ncc_gbs / MI355X_HBM_GBS, 4),
                bytes_per_launch=ncc_bytes,
@@ -348,20 +411,20 @@ def run(args):
                # plain device fill of the same size measured in this run
                achievable=hbm, frac_of_achievable_write=round(ncc_gbs / hbm["fill_gbs"], 4))
 
-    # cost + filter together (NCC + both aggregations): the binding bound is the
-    # larger of their compute time (NCC on the vector ALU; the aggregation on
-    # the vector ALU or the matrix cores, which do not issue alongside vector
-    # ALU work on a SIMD, so the two times add) and the HBM time of their bytes
+    # cost + filter together (NCC + both aggregations), read as a roofline of
+    # the method: its FP32 work (8 flops per element for the NCC, 2 (2R+1)^2
+    # + 1 per element and volume for the aggregation) at the published FP32
+    # rate, against the HBM time of the bytes this engine materialises (the
+    # volumes written once and read once); the larger of the two binds
     t_meas = st["ncc_ms"] + st["aggregate_wta_ref_ms"] + st["aggregate_wta_tar_ms"]
-    ncc_flops = 8.0 * w.num_disp * H * (W + w.num_disp - 1)
-    cf_bytes = ncc_bytes + 2 * 4.0 * elements
-    agg_peak = MI355X_FP32_MFMA_TFLOPS if engine == 1 else MI355X_FP32_VALU_TFLOPS
-    t_comp = (ncc_flops / (MI355X_FP32_VALU_TFLOPS * 1e12) +
-              2 * flops_per_launch / (agg_peak * 1e12)) * 1e3
+    model_flops = (8.0 + 2 * (2.0 * taps + 1)) * elements
+    cf_bytes = 2 * ncc_bytes if engine == 2 else ncc_bytes + 2 * 4.0 * elements
+    t_comp = model_flops / (MI355X_FP32_MFMA_TFLOPS * 1e12) * 1e3
     t_hbm = cf_bytes / (MI355X_HBM_GBS * 1e9) * 1e3
     cost_filter = dict(stages="ncc + aggregation of both volumes", measured_ms=round(t_meas, 4),
                        compute_bound_ms=round(t_comp, 4), hbm_bound_ms=round(t_hbm, 4),
-                       binding=("mfma+alu" if engine == 1 else "alu") if t_comp >= t_hbm else "hbm",
+                       model_flops=model_flops, materialised_bytes=cf_bytes,
+                       binding="fp32 compute" if t_comp >= t_hbm else "hbm",
                        frac=round(max(t_comp, t_hbm) / t_meas, 4))
 
     value = elements / (ms / 1e3) / 1e9
@@ -584,6 +647,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=240)
     ap.add_argument("--no-extra", dest="extra", action="store_false")
+    ap.add_argument("--serial-inputs", action="store_true",
+                    help="generate the batch inputs in this process (runs under a profiler)")
     ap.add_argument("--tune", action="append", default=[],
                     help="plan tuning key=value (e.g. agg_levels_f32=16)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,

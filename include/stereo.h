@@ -125,9 +125,14 @@ stereo_status stereo_plan_set_homography(stereo_plan_t plan, const double* H);
  * Launch-shape choices.  Keys:
  *   "agg_engine": the kernel of the fused aggregation and selection
  *   (stereo_match, Eq. 9-11 and 13) and of the soft-argmin forward
- *   (stereo_soft_forward): 1 (default) the matrix cores, 0 the vector ALU;
- *   the two sum in different orders, so they agree to FP32 rounding (a
- *   disparity can differ at a near tie), not bit for bit;
+ *   (stereo_soft_forward): 2 (default) the matrix cores with FP16 operands
+ *   split in two (each cost and weight carried as the sum of two FP16
+ *   numbers, three FP16 products per term, FP32 accumulation: as accurate
+ *   as FP32 products), 1 the matrix cores with FP32 operands, 0 the vector
+ *   ALU.  With 2 the NCC stage writes the reference- and target-anchored
+ *   volumes in that split form; with 0 and 1 one FP32 volume.  The engines
+ *   sum in different orders, so they agree to FP32 rounding (a disparity
+ *   can differ at a near tie), not bit for bit;
  *   "agg_levels_u8", "agg_levels_f32": disparity levels staged per pass of
  *   the vector-ALU aggregation kernel for 8-bit / float guides, 8 or 16
  *   (default 8); results are bitwise identical for every value;
@@ -308,9 +313,9 @@ typedef struct {
 stereo_status stereo_batch_create(const stereo_batch_item* items, int32_t n,
                                   stereo_batch_t* out);
 stereo_status stereo_batch_workspace_bytes(stereo_batch_t b, size_t* bytes);
-/* Tuning keys: "agg_engine" (as for a plan: 1 matrix cores, default, or 0
- * vector ALU; a batch gives the same bits as its pairs' stereo_match when
- * both use the same engine), "wg_per_cu" (persistent workgroups per CU of
+/* Tuning keys: "agg_engine" (as for a plan: 2, default, 1 or 0; a batch
+ * gives the same bits as its pairs' stereo_match when both use the same
+ * engine), "wg_per_cu" (persistent workgroups per CU of
  * the vector-ALU engine, 1..8, default 2), "agg_levels_u8", "agg_levels_f32"
  * (8 or 16).  Drops an instantiated graph. */
 stereo_status stereo_batch_set_tuning(stereo_batch_t b, const char* key, int32_t value);

@@ -94,7 +94,13 @@ void layout(Plan& P) {
   size_t o = 0;
   P.off_tarw = o;  o = align256(o + sizeof(float) * (size_t)W * H);
   P.off_stats = o; o = align256(o + sizeof(float) * 4 * (size_t)P.stats_w * H);
-  P.off_cvol = o;  o = align256(o + sizeof(float) * 4 * (size_t)((D + 3) / 4) * H * P.cw);
+  // the cost volume region holds either the quad-interleaved FP32 volume
+  // (engines 0 and 1) or the two split-FP16 volumes (engine 2)
+  P.h2_pitch = h2_pitch(P.R, W);
+  P.h2_tar_off = align256(sizeof(uint16_t) * 2 * 16 * (size_t)((D + 15) / 16) * H * P.h2_pitch);
+  const size_t quad_bytes = sizeof(float) * 4 * (size_t)((D + 3) / 4) * H * P.cw;
+  const size_t h2_bytes = 2 * P.h2_tar_off;
+  P.off_cvol = o;  o = align256(o + (quad_bytes > h2_bytes ? quad_bytes : h2_bytes));
   P.off_dT = o;    o = align256(o + sizeof(int16_t) * (size_t)W * H);
   P.off_dsub = o;  o = align256(o + sizeof(float) * (size_t)W * H);
   P.off_road = o;  o = align256(o + sizeof(double) * 10 * (size_t)P.road_blocks);
@@ -221,7 +227,9 @@ stereo_status stereo_plan_set_tuning(stereo_plan_t plan, const char* key, int32_
     return STEREO_OK;
   }
   if (k == "agg_engine") {
-    STEREO_REQUIRE(value == 0 || value == 1, "agg_engine must be 0 (vector ALU) or 1 (matrix cores)");
+    STEREO_REQUIRE(value >= 0 && value <= 2,
+                   "agg_engine must be 0 (vector ALU), 1 (matrix cores, FP32 operands) or 2 "
+                   "(matrix cores, split-FP16 operands)");
     plan->P.agg_engine = value;
     return STEREO_OK;
   }
@@ -358,20 +366,39 @@ stereo_status match_impl(stereo_plan_t plan, const void* ref, const void* tar,
   STEREO_HIP(launch_block_stats(P, tarw, STEREO_F32, P.W, m.zY, m.isdY, stream),
              "block statistics (tar_w)");
   STEREO_HIP(mark(2), "event record");
-  // One reference-anchored volume over the extended columns [0, W + D - 1):
-  // the target volume is its re-indexing C_T(x, d) = C_R(x + d, d).  Stored
-  // as float4 quads of consecutive levels (slice and pitch in float4 units).
-  const int64_t slice = (int64_t)P.H * P.cw;
-  const int ext_w = P.W + P.D - 1;
-  STEREO_HIP(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, cvol, ext_w, P.cw, slice,
-                        0, stream, 0, -1, 1), "ncc");
-  STEREO_HIP(mark(3), "event record");
+  const bool lr = P.p.lr_check != 0;
   BilArgs a{};
-  a.C = cvol;
-  a.c_slice = slice;
-  a.c_pitch = P.cw;
-  a.shift = 0;
-  a.quad = 1;
+  if (P.agg_engine == 2) {
+    // Split-FP16 volumes for the FP16-operand matrix cores, one NCC launch
+    // per anchor: the reference-anchored volume and, for the LR check, the
+    // target-anchored one (each stored by the column it is aggregated at).
+    uint16_t* vR = at<uint16_t>(ws, P.off_cvol);
+    uint16_t* vT = at<uint16_t>(ws, P.off_cvol + P.h2_tar_off);
+    const int64_t plane = 16 * (int64_t)P.H * P.h2_pitch;
+    STEREO_HIP(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, reinterpret_cast<float*>(vR),
+                          P.h2_pitch, P.h2_pitch, plane, 0, stream, 0, -1, 2, P.R), "ncc");
+    if (lr)
+      STEREO_HIP(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY,
+                            reinterpret_cast<float*>(vT), P.h2_pitch, P.h2_pitch, plane, 1,
+                            stream, 0, -1, 2, P.R), "ncc (target-anchored)");
+    a.h2 = vR;
+    a.h2_plane = plane;
+    a.h2_pitch = P.h2_pitch;
+  } else {
+    // One reference-anchored volume over the extended columns [0, W + D - 1):
+    // the target volume is its re-indexing C_T(x, d) = C_R(x + d, d).  Stored
+    // as float4 quads of consecutive levels (slice and pitch in float4 units).
+    const int64_t slice = (int64_t)P.H * P.cw;
+    const int ext_w = P.W + P.D - 1;
+    STEREO_HIP(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, cvol, ext_w, P.cw, slice,
+                          0, stream, 0, -1, 1), "ncc");
+    a.C = cvol;
+    a.c_slice = slice;
+    a.c_pitch = P.cw;
+    a.shift = 0;
+    a.quad = 1;
+  }
+  STEREO_HIP(mark(3), "event record");
   a.guide = ref;
   a.guide_dt = P.p.dtype;
   a.guide_pitch = P.p.pitch_ref;
@@ -379,10 +406,10 @@ stereo_status match_impl(stereo_plan_t plan, const void* ref, const void* tar,
   a.dsub = ds;
   STEREO_HIP(launch_bilateral(P, a, 1, stream), "bilateral + WTA (reference)");
   STEREO_HIP(mark(4), "event record");
-  const bool lr = P.p.lr_check != 0;
   if (lr) {
     BilArgs b = a;
-    b.shift = 1;
+    if (a.h2) b.h2 = at<uint16_t>(ws, P.off_cvol + P.h2_tar_off);
+    else b.shift = 1;
     b.guide = tarw;
     b.guide_dt = STEREO_F32;
     b.guide_pitch = P.W;

@@ -64,7 +64,8 @@ struct stereo_batch_s {
   void* bound_ws = nullptr;
   int wg_per_cu = 2;
   int levels_u8 = 8, levels_f32 = 8;
-  int engine = 1;                      // aggregation engine: 1 matrix cores, 0 vector ALU
+  int engine = 2;                      // aggregation engine: 2 / 1 matrix cores with split-FP16
+                                       // / FP32 operands, 0 vector ALU
   int cu_count = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -81,6 +82,27 @@ namespace {
 template <typename T>
 T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// Block prefix of the NCC job lists for the batch's engine: the quad volume
+// covers the extended columns (anchor 0 only), the split-FP16 volumes the
+// stored rows of both anchors (the target-anchored one when the pair has an
+// LR check).
+void ncc_blocks(stereo_batch_s& b) {
+  for (JobList& L : b.lists) {
+    if (L.kind != JK_NCC) continue;
+    for (size_t k = 0; k < L.pair.size(); ++k) {
+      const Plan& P = b.plans[L.pair[k]];
+      int blocks = 0;
+      if (b.engine == 2) {
+        if (L.which[k] == 0 || P.p.lr_check)
+          blocks = ncc_job_blocks(P, P.h2_pitch, 0, P.D, L.dc);
+      } else if (L.which[k] == 0) {
+        blocks = ncc_job_blocks(P, P.W + P.D - 1, 0, P.D, L.dc);
+      }
+      L.first[k + 1] = L.first[k] + blocks;
+    }
+  }
 }
 
 void build_layout(stereo_batch_s& b) {
@@ -165,21 +187,18 @@ void build_layout(stereo_batch_s& b) {
     Lt.r = std::max(Lt.r, P.r);
   }
   // NCC: the level block of the list's smallest pair (the smallest block that
-  // holds its levels, at most 64), then the blocks
+  // holds its levels, at most 64); two jobs per pair (which = the anchor:
+  // the target-anchored one runs only for the split-FP16 engine), their
+  // blocks set per engine by ncc_blocks
   for (int i = 0; i < n; ++i) {
     const Plan& P = b.plans[i];
     JobList& L = list_of(JK_NCC, P.p.dtype, P.r);
     const int dc = P.D > 32 ? 64 : P.D > 16 ? 32 : 16;
     L.dc = L.pair.empty() ? dc : std::min(L.dc, dc);
     push(L, i, 0, 0);
+    push(L, i, 1, 0);
   }
-  for (JobList& L : b.lists) {
-    if (L.kind != JK_NCC) continue;
-    for (size_t k = 0; k < L.pair.size(); ++k) {
-      const Plan& P = b.plans[L.pair[k]];
-      L.first[k + 1] = L.first[k] + ncc_job_blocks(P, P.W + P.D - 1, 0, P.D, L.dc);
-    }
-  }
+  ncc_blocks(b);
   for (int i = 0; i < n; ++i)
     if (b.items[i].valid || b.items[i].disp)
       push(list_of(JK_LR, STEREO_F32, 0), i, 0, lr_job_blocks(b.plans[i]));
@@ -211,11 +230,17 @@ stereo_status bind(stereo_batch_s& b, void* ws, size_t bytes, hipStream_t s) {
     const Plan& P = b.plans[i];
     void* pws = at<char>(ws, b.pair_ws[i]);
     BilArgs a{};
-    a.C = at<float>(pws, P.off_cvol);
-    a.c_slice = (int64_t)P.H * P.cw;
-    a.c_pitch = P.cw;
-    a.shift = 0;
-    a.quad = 1;
+    if (b.engine == 2) {
+      a.h2 = at<uint16_t>(pws, P.off_cvol);
+      a.h2_plane = 16 * (int64_t)P.H * P.h2_pitch;
+      a.h2_pitch = P.h2_pitch;
+    } else {
+      a.C = at<float>(pws, P.off_cvol);
+      a.c_slice = (int64_t)P.H * P.cw;
+      a.c_pitch = P.cw;
+      a.shift = 0;
+      a.quad = 1;
+    }
     a.guide = b.items[i].ref;
     a.guide_dt = P.p.dtype;
     a.guide_pitch = P.p.pitch_ref;
@@ -223,7 +248,8 @@ stereo_status bind(stereo_batch_s& b, void* ws, size_t bytes, hipStream_t s) {
     a.dsub = at<float>(pws, P.off_dsub);
     bilateral_pair(P, a, b.host_desc.data() + (2 * i) * pb);
     BilArgs t = a;
-    t.shift = 1;
+    if (b.engine == 2) t.h2 = at<uint16_t>(pws, P.off_cvol + P.h2_tar_off);
+    else t.shift = 1;
     t.guide = at<float>(pws, P.off_tarw);
     t.guide_dt = STEREO_F32;
     t.guide_pitch = P.W;
@@ -234,6 +260,7 @@ stereo_status bind(stereo_batch_s& b, void* ws, size_t bytes, hipStream_t s) {
   BHIP(hipMemcpyAsync(at<char>(ws, b.desc_off), b.host_desc.data(), b.desc_bytes,
                       hipMemcpyHostToDevice, s), "upload descriptors");
   // job descriptors of the cheap stages
+  ncc_blocks(b);
   std::vector<std::vector<char>> host_jobs(b.lists.size());
   for (size_t li = 0; li < b.lists.size(); ++li) {
     const JobList& L = b.lists[li];
@@ -256,9 +283,19 @@ stereo_status bind(stereo_batch_s& b, void* ws, size_t bytes, hipStream_t s) {
             : stats_job(P, tarw, P.W, st + 2 * sn, st + 3 * sn);
         memcpy(dst, &J, sizeof(J));
       } else if (L.kind == JK_NCC) {
-        const NccJob J = ncc_job(P, b.items[i].ref, tarw, st, st + sn, st + 2 * sn, st + 3 * sn,
-                                 at<float>(pws, P.off_cvol), P.W + P.D - 1, P.cw,
-                                 (int64_t)P.H * P.cw, 0, 0, P.D);
+        NccJob J;
+        if (b.engine == 2) {
+          // anchor = which: the reference- or the target-anchored volume
+          const int anchor = L.which[k];
+          J = ncc_job(P, b.items[i].ref, tarw, st, st + sn, st + 2 * sn, st + 3 * sn,
+                      at<float>(pws, P.off_cvol + (anchor ? P.h2_tar_off : 0)), P.h2_pitch,
+                      P.h2_pitch, 16 * (int64_t)P.H * P.h2_pitch, anchor, 0, P.D);
+          J.pad = P.R;
+        } else {
+          J = ncc_job(P, b.items[i].ref, tarw, st, st + sn, st + 2 * sn, st + 3 * sn,
+                      at<float>(pws, P.off_cvol), P.W + P.D - 1, P.cw, (int64_t)P.H * P.cw, 0,
+                      0, P.D);
+        }
         memcpy(dst, &J, sizeof(J));
       } else {
         const LrJob J = lr_job(P, b.items[i].dint_R,
@@ -302,8 +339,9 @@ stereo_status enqueue(stereo_batch_s& b, hipStream_t s) {
                                s), "batch statistics");
         break;
       case JK_NCC:
-        BHIP(launch_ncc_jobs(L.r, L.dt, 1, L.dc, static_cast<const NccJob*>(jobs), first, nj, blocks,
-                             s), "batch ncc");
+        BHIP(launch_ncc_jobs(L.r, L.dt, b.engine == 2 ? 2 : 1, L.dc,
+                             static_cast<const NccJob*>(jobs), first, nj, blocks, s),
+             "batch ncc");
         break;
       case JK_LR:
         BHIP(launch_lr_jobs(static_cast<const LrJob*>(jobs), first, nj, blocks, s),
@@ -326,11 +364,12 @@ stereo_status enqueue(stereo_batch_s& b, hipStream_t s) {
   const void* desc = at<char>(ws, b.desc_off);
   for (int g = 0; g < ng; ++g) {
     const Group& G = b.groups[g];
-    if (b.engine == 1) {                 // one workgroup per CU holds the whole LDS
+    if (b.engine >= 1) {                 // one workgroup per CU holds the whole LDS
       const int nt = (int)G.tiles_m.size() / 3;
       const int groups = std::max(1, std::min(nt, b.cu_count));
-      BHIP(launch_bilateral_persistent(1, G.R, G.gdt, G.levels, desc, at<int>(ws, G.tiles_m_off), nt,
-                                       ctr + g, groups, s), "batch aggregation");
+      BHIP(launch_bilateral_persistent(b.engine, G.R, G.gdt, G.levels, desc,
+                                       at<int>(ws, G.tiles_m_off), nt, ctr + g, groups, s),
+           "batch aggregation");
     } else {
       const int nt = (int)G.tiles.size() / 3;
       const int groups = std::max(1, std::min(nt, b.cu_count * b.wg_per_cu));
@@ -403,8 +442,11 @@ stereo_status stereo_batch_set_tuning(stereo_batch_t b, const char* key, int32_t
     (k == "agg_levels_u8" ? b->levels_u8 : b->levels_f32) = value;
     for (Group& G : b->groups) G.levels = G.gdt == STEREO_U8 ? b->levels_u8 : b->levels_f32;
   } else if (k == "agg_engine") {
-    BREQ(value == 0 || value == 1, "agg_engine must be 0 (vector ALU) or 1 (matrix cores)");
+    BREQ(value >= 0 && value <= 2,
+         "agg_engine must be 0 (vector ALU), 1 (matrix cores, FP32 operands) or 2 (matrix "
+         "cores, split-FP16 operands)");
     b->engine = value;
+    b->bound_ws = nullptr;              // descriptors and NCC jobs depend on the engine
   } else {
     return fail(STEREO_ERR_INVALID_ARGUMENT, "unknown batch tuning key '%s'", key);
   }

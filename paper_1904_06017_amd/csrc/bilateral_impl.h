@@ -91,6 +91,9 @@ struct BilPair {
   int W, H, D;
   float ks2, kr2;
   BilOut o;
+  const uint16_t* h2;               // split-FP16 volume (see BilArgs)
+  int64_t h2_plane;
+  int h2_pitch;
 };
 
 template <typename G>
@@ -497,6 +500,7 @@ inline BilPair make_pair(const Plan& P, const BilArgs& a) {
   o.gD = a.gD; o.cpix = a.cpix; o.aP = a.aP; o.A1 = a.A1; o.A2 = a.A2; o.Wp = a.Wp;
   o.d_first = a.d_first;
   o.one_minus_c1 = (float)(1.0 - a.plane[1]);
+  b.h2 = a.h2; b.h2_plane = a.h2_plane; b.h2_pitch = a.h2_pitch;
   return b;
 }
 

@@ -41,7 +41,10 @@ struct Plan {
   double Hm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   int ncc_levels = 0;   // levels per NCC workgroup (16, 32 or 64; DC / 4 waves);
                         // 0: 64 / 32 / 16 by the levels of the launch
-  int agg_engine = 1;   // fused aggregation + selection: 1 matrix cores, 0 vector ALU
+  int agg_engine = 2;   // fused aggregation + selection: 2 matrix cores with split
+                        // FP16 operands, 1 matrix cores with FP32 operands, 0 vector ALU
+  int h2_pitch = 0;     // row pitch (halves) of the split-FP16 volumes
+  size_t h2_tar_off = 0;  // byte offset of the target-anchored one in the volume region
   // differentiable form (F32 plans): levels recomputed per backward tile and
   // the workspace regions it uses (offsets from the workspace base)
   int grad_levels = 16;  // set from D at plan creation
@@ -89,12 +92,15 @@ hipError_t launch_block_stats(const Plan& P, const void* img, stereo_dtype dt,
 // ref statistics in (zX, isdX), tar_w statistics in (zY, isdY).
 // Levels [d_first, d_end) (d_end < 0: all D), written to slice d - d_first.
 // quad = 1: level-quad-interleaved float4 layout [levels/4][H][out_pitch]
-// (out_slice, out_pitch in float4 units; d_first a multiple of 4).
+// (out_slice, out_pitch in float4 units; d_first a multiple of 4).  quad = 2:
+// split-FP16 volume of the anchor (see BilArgs::h2), out_pitch = stored
+// columns (a multiple of 8), out_slice = 16 H out_pitch, out_w >= out_pitch,
+// pad = column shift (the window radius R), d_first a multiple of 16.
 hipError_t launch_ncc(const Plan& P, const void* ref, const float* tar_w,
                       const float* zX, const float* isdX, const float* zY,
                       const float* isdY, float* C, int out_w, int64_t out_pitch,
                       int64_t out_slice, int anchor, hipStream_t s, int d_first = 0,
-                      int d_end = -1, int quad = 0);
+                      int d_end = -1, int quad = 0, int pad = 0);
 
 struct BilArgs {
   const float* C;     // planar: C[d * c_slice + y * c_pitch + x + d*shift]
@@ -122,6 +128,15 @@ struct BilArgs {
   float* A2;          // mode 6: += sum_q w (G(q)-G(p)) sum_d dE(q,d)/W_q C(p,d)
   float* Wp;          // mode 5 (nullable): sum_q w(p, q)
   int d_first;        // modes 5, 6: level of the tile's first slice
+  // split-FP16 volume of the matrix-core engine with FP16 operands (modes 1,
+  // 2; used when non-NULL), in blocks of 16 levels: level d of column x at
+  // h2[(2 (d >> 4) + part) * h2_plane + 16 y h2_pitch + 64 (s >> 2) +
+  // 4 (d & 15) + (s & 3)], s = x + R; part 0 = FP16 value c_hi of the cost,
+  // part 1 = FP16 value of c - c_hi; columns outside [0, W) and the last
+  // block's levels past D hold zeros
+  const uint16_t* h2;
+  int64_t h2_plane;   // halves per block part (>= 16 H h2_pitch)
+  int h2_pitch;       // columns per stored row (a multiple of 8)
 };
 // mode 0: write the normalised aggregated volume; mode 1: fused WTA and
 // sub-pixel refinement (the volume never leaves the chip); mode 2: fused
@@ -132,6 +147,16 @@ struct BilArgs {
 // E out = dC = sum_q w C, and A2), float guides only.
 hipError_t launch_bilateral(const Plan& P, const BilArgs& a, int mode,
                             hipStream_t s);
+
+// Row pitch (halves, a multiple of 8) of the split-FP16 volumes at window
+// radius R for width W: covers the halo columns of every 16-pixel tile.
+int h2_pitch(int R, int W);
+// Columns (and so blocks) of a batched NCC job: the extended range
+// [0, W + D - 1) of the quad volume or the stored row of a split-FP16 volume.
+inline int ncc_out_w(const Plan& P) {
+  const int ext = P.W + P.D - 1;
+  return ext > P.h2_pitch ? ext : P.h2_pitch;
+}
 
 // Persistent aggregation (mode 1, fused WTA) over a queue of tiles of many
 // pairs: pairs = device array of per-pair descriptors (bilateral_pair), tiles
@@ -179,6 +204,7 @@ struct NccJob {             // grid: gx = ceil(out_w / 64) x gy = ceil(H / 32) x
   const float *zX, *isdX, *zY, *isdY;
   float* C; int64_t out_pitch, out_slice;
   int W, H, d_first, d_end, out_w, anchor, gx, gy;
+  int pad;                    // split-FP16 output (quad = 2): column shift
 };
 struct LrJob {              // grid: gx = ceil(W / 256) x H rows
   const int16_t* dR; const int16_t* dT; const float* dsub; uint8_t* valid; float* disp;

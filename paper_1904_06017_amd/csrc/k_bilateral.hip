@@ -1,5 +1,5 @@
 // Dispatch of the aggregation launches over the compiled window radii.
-#include "bilateral_impl.h"
+#include "bilateral_mfma16.h"
 
 namespace stereo {
 hipError_t launch_bilateral_r1(const Plan&, const BilArgs&, int, hipStream_t);
@@ -50,6 +50,20 @@ hipError_t launch_bilateral_persistent(int engine, int R, stereo_dtype gdt, int 
 }
 
 size_t bilateral_pair_bytes() { return sizeof(bil::BilPair); }
+
+int h2_pitch(int R, int W) {
+  switch (R) {
+    case 1: return bilh::h2_pitch_for<1>(W);
+    case 2: return bilh::h2_pitch_for<2>(W);
+    case 3: return bilh::h2_pitch_for<3>(W);
+    case 4: return bilh::h2_pitch_for<4>(W);
+    case 5: return bilh::h2_pitch_for<5>(W);
+    case 6: return bilh::h2_pitch_for<6>(W);
+    case 7: return bilh::h2_pitch_for<7>(W);
+    case 8: return bilh::h2_pitch_for<8>(W);
+    default: return 0;
+  }
+}
 
 void* bilateral_pair(const Plan& P, const BilArgs& a, void* out) {
   *static_cast<bil::BilPair*>(out) = bil::make_pair(P, a);

@@ -1,8 +1,9 @@
 // Aggregation kernels instantiated for window radius R = 7.
-#include "bilateral_mfma.h"
+#include "bilateral_mfma16.h"
 
 namespace stereo {
 hipError_t launch_bilateral_r7(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
+  if ((mode == 1 || mode == 2) && a.h2) return bilh::launch_args<7>(P, a, mode, s);
   if ((mode == 1 || mode == 2) && P.agg_engine == 1 && a.quad)
     return bilm::launch_args<7>(P, a, mode, s);
   return bil::launch_r<7>(P, a, mode, s);
@@ -11,6 +12,7 @@ hipError_t launch_bilateral_persistent_r7(int engine, stereo_dtype gdt, int leve
                                            const int* tiles, int n_tiles, unsigned int* counter,
                                            int n_groups, hipStream_t s) {
   const bil::BilPair* p = static_cast<const bil::BilPair*>(pairs);
+  if (engine == 2) return bilh::launch_queue_r<7>(gdt, p, tiles, n_tiles, counter, n_groups, s);
   if (engine == 1) return bilm::launch_queue_r<7>(gdt, p, tiles, n_tiles, counter, n_groups, s);
   return bil::launch_persistent_r<7>(gdt, levels, p, tiles, n_tiles, counter, n_groups, s);
 }

@@ -208,7 +208,54 @@ struct NccGeom {
 // QUAD = 1 writes the level-quad-interleaved layout [levels/4][H][pitch]
 // float4 (out_slice and out_pitch in float4 units; levels at or past d_end
 // inside the last quad are written as 0), QUAD = 0 the planar layout
-// [levels][H][pitch].
+// [levels][H][pitch].  QUAD = 2 writes the split-FP16 volumes of the
+// FP16-operand matrix-core aggregation (anchor 0 over the extended columns,
+// d_first = 0): blocks of 16 levels, each [part][H][pitch / 4 column quads]
+// [16 levels][4 columns] halves, i.e. level d of stored column s = x + pad at
+// ((2 (d >> 4) + part) H + y) 16 pitch + 64 (s >> 2) + 4 (d & 15) + (s & 3),
+// out_slice = 16 H pitch, out_pitch = pitch; part 0 = FP16 rounding of the
+// cost, part 1 = FP16 rounding of the remainder; the anchor decides which
+// volume (0: reference-anchored, 1: target-anchored).  The tiles start pad
+// columns left of their 64-column boundary, so a lane quad is a stored column
+// quad and, after a transpose within the quad, each lane writes 4 columns of
+// one level as 8 bytes; the grid's columns cover the stored row
+// (out_w >= out_pitch), columns outside [0, W) and the last block's levels at
+// or past d_end are written as zeros.
+// 4x4 transpose within each quad of lanes (lane c of a quad holds v[0..3];
+// afterwards v[k] holds what lane k held in element c): two butterfly stages
+// of DPP quad permutations, swapping the off-diagonal 2x2 blocks.
+__device__ __forceinline__ float dpp_quad_xor1(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float dpp_quad_xor2(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x4E, 0xF, 0xF, false));
+}
+__device__ __forceinline__ void quad_transpose4(float (&v)[4], int lane) {
+  const bool b0 = lane & 1, b1 = lane & 2;
+  float t[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) t[k] = dpp_quad_xor1(v[k ^ 1]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = (b0 != (bool)(k & 1)) ? t[k] : v[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) t[k] = dpp_quad_xor2(v[k ^ 2]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = (b1 != (bool)(k & 2)) ? t[k] : v[k];
+}
+
+// v = hi + lo in FP16 (round to nearest; lo rounds the exact remainder),
+// four values packed two per register.
+__device__ __forceinline__ void split4_f16(const float (&v)[4], uint2& hi, uint2& lo) {
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  const h2 h01 = __builtin_convertvector((f2){v[0], v[1]}, h2);
+  const h2 h23 = __builtin_convertvector((f2){v[2], v[3]}, h2);
+  const h2 l01 = __builtin_convertvector((f2){v[0] - (float)h01.x, v[1] - (float)h01.y}, h2);
+  const h2 l23 = __builtin_convertvector((f2){v[2] - (float)h23.x, v[3] - (float)h23.y}, h2);
+  hi = make_uint2(__builtin_bit_cast(unsigned, h01), __builtin_bit_cast(unsigned, h23));
+  lo = make_uint2(__builtin_bit_cast(unsigned, l01), __builtin_bit_cast(unsigned, l23));
+}
+
 template <int r, typename T, int QUAD, int DC>
 __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_pitch,
                                          const float* __restrict__ tarw, int W, int H,
@@ -218,7 +265,7 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
                                          const float* __restrict__ zY,
                                          const float* __restrict__ isdY,
                                          float* __restrict__ C, int out_w, int64_t out_pitch,
-                                         int64_t out_slice, int anchor, float* sm, int bx,
+                                         int64_t out_slice, int anchor, int pad, float* sm, int bx,
                                          int by, int bz) {
   using G = NccGeom<r, DC>;
   constexpr int K = G::K;
@@ -226,7 +273,9 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
   float* Bs = sm + G::ROWS * G::AW;       // [ROWS][BW]
   float* Zs = Bs + G::ROWS * G::BW;       // [NC_TY][ZW]: z of the B side
   float* Is = Zs + NC_TY * G::ZW;         // [NC_TY][ZW]: 1/sd of the B side
-  const int x0 = bx * NC_TX;
+  // split-FP16 output: the tile starts pad columns left of 64 bx, so that
+  // lane l writes stored column 64 bx + l and a lane quad is a column quad
+  const int x0 = bx * NC_TX - (QUAD == 2 ? pad : 0);
   const int y0 = by * NC_TY;
   const int d0 = d_first + bz * DC;
   const int SW = W + 2 * r;
@@ -280,7 +329,7 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
   for (int k = 0; k < NC_DW; ++k)
 #pragma unroll
     for (int i = 0; i < K; ++i) ring[k][i] = 0.0f;
-  const int cx = min(x, W - 1 + r) + r;       // centre of the A block in the maps
+  const int cx = min(max(x, -r), W - 1 + r) + r;   // centre of the A block in the maps
 
   for (int yb = 0; yb < G::ROWS; yb += K) {
 #pragma unroll
@@ -304,7 +353,7 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
           ring[k][s] = h;
         }
         const int y = y0 + yy - 2 * r;        // output row completed by this input row
-        if (yy >= 2 * r && y < H && x < out_w) {
+        if (yy >= 2 * r && y < H && (QUAD == 2 ? x + pad < out_pitch : x < out_w)) {
           const int64_t rowo = (int64_t)y * SW;
           const float zA = anchor ? zY[rowo + cx] : zX[rowo + cx];
           const float iA = (anchor ? isdY[rowo + cx] : isdX[rowo + cx]) * inv_n;
@@ -325,11 +374,31 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
             if (!QUAD)
               C[(int64_t)(d - d_first) * out_slice + (int64_t)y * out_pitch + x] = cq[k];
           }
-          if (QUAD) {
+          if (QUAD == 1) {
             const int q = (d0 + wave * NC_DW - d_first) >> 2;
             if (d0 + wave * NC_DW < d_end)
               reinterpret_cast<float4*>(C)[(int64_t)q * out_slice + (int64_t)y * out_pitch + x] =
                   make_float4(cq[0], cq[1], cq[2], cq[3]);
+          }
+          if (QUAD == 2) {
+            // this wave's 4 levels of the lane quad's 4 columns, transposed so
+            // that lane c of the quad holds level 4 wave + c of all 4 columns;
+            // columns outside the image and levels past d_end are zeros
+            float v[NC_DW];
+#pragma unroll
+            for (int k = 0; k < NC_DW; ++k) v[k] = (x >= 0 && x < W) ? cq[k] : 0.0f;
+            quad_transpose4(v, lane);
+            const int dl = d0 + wave * NC_DW + (lane & 3);
+            if (dl < ((d_end + 15) & ~15)) {
+              uint2 hi, lo;
+              split4_f16(v, hi, lo);
+              // stored column quad 16 bx + lane / 4 of row y, level dl
+              const int64_t off = (int64_t)(2 * ((dl - d_first) >> 4)) * out_slice +
+                                  (int64_t)y * 16 * out_pitch + 64 * (16 * bx + (lane >> 2)) +
+                                  4 * (dl & 15);
+              *reinterpret_cast<uint2*>(reinterpret_cast<_Float16*>(C) + off) = hi;
+              *reinterpret_cast<uint2*>(reinterpret_cast<_Float16*>(C) + out_slice + off) = lo;
+            }
           }
         }
       }
@@ -344,10 +413,10 @@ ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
            const float* __restrict__ zX, const float* __restrict__ isdX,
            const float* __restrict__ zY, const float* __restrict__ isdY,
            float* __restrict__ C, int out_w, int64_t out_pitch,
-           int64_t out_slice, int anchor) {
+           int64_t out_slice, int anchor, int pad) {
   extern __shared__ float sm[];
   ncc_body<r, T, QUAD, DC>(ref, ref_pitch, tarw, W, H, d_first, d_end, zX, isdX, zY, isdY, C,
-                       out_w, out_pitch, out_slice, anchor, sm, blockIdx.x, blockIdx.y,
+                       out_w, out_pitch, out_slice, anchor, pad, sm, blockIdx.x, blockIdx.y,
                        blockIdx.z);
 }
 
@@ -398,7 +467,7 @@ ncc_jobs_kernel(const NccJob* __restrict__ jobs, const int* __restrict__ first, 
   const int bz = l / gxy, rem = l - bz * gxy;
   ncc_body<r, T, QUAD, DC>(static_cast<const T*>(J.ref), J.ref_pitch, J.tarw, J.W, J.H, J.d_first,
                        J.d_end, J.zX, J.isdX, J.zY, J.isdY, J.C, J.out_w, J.out_pitch,
-                       J.out_slice, J.anchor, sm, rem % J.gx, rem / J.gx, bz);
+                       J.out_slice, J.anchor, J.pad, sm, rem % J.gx, rem / J.gx, bz);
 }
 
 // Dynamic LDS above the 64 KB default (large radii at 64 levels), set once
@@ -421,21 +490,28 @@ template <int r, typename T, int DC>
 hipError_t launch_ncc_rdc(const Plan& P, const T* ref, const float* tar_w, const float* zX,
                           const float* isdX, const float* zY, const float* isdY, float* C,
                           int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
-                          int d_first, int d_end, int quad, hipStream_t s) {
+                          int d_first, int d_end, int quad, int pad,
+                          hipStream_t s) {
   dim3 grid((out_w + NC_TX - 1) / NC_TX, (P.H + NC_TY - 1) / NC_TY,
             (d_end - d_first + DC - 1) / DC);
-  hipError_t e = quad ? ncc_allow_lds<r, T, 1, DC, 0>() : ncc_allow_lds<r, T, 0, DC, 0>();
+  hipError_t e = quad == 2 ? ncc_allow_lds<r, T, 2, DC, 0>()
+                 : quad ? ncc_allow_lds<r, T, 1, DC, 0>() : ncc_allow_lds<r, T, 0, DC, 0>();
   if (e != hipSuccess) return e;
-  if (quad)
+  if (quad == 2)
+    hipLaunchKernelGGL((ncc_kernel<r, T, 2, DC>), grid, dim3(16 * DC),
+                       (NccGeom<r, DC>::lds_bytes), s, ref, P.p.pitch_ref, tar_w, P.W, P.H,
+                       d_first, d_end, zX, isdX, zY, isdY, C, out_w, out_pitch, out_slice,
+                       anchor, pad);
+  else if (quad)
     hipLaunchKernelGGL((ncc_kernel<r, T, 1, DC>), grid, dim3(16 * DC),
                        (NccGeom<r, DC>::lds_bytes), s, ref, P.p.pitch_ref, tar_w, P.W, P.H,
                        d_first, d_end, zX, isdX, zY, isdY, C, out_w, out_pitch, out_slice,
-                       anchor);
+                       anchor, 0);
   else
     hipLaunchKernelGGL((ncc_kernel<r, T, 0, DC>), grid, dim3(16 * DC),
                        (NccGeom<r, DC>::lds_bytes), s, ref, P.p.pitch_ref, tar_w, P.W, P.H,
                        d_first, d_end, zX, isdX, zY, isdY, C, out_w, out_pitch, out_slice,
-                       anchor);
+                       anchor, 0);
   return hipGetLastError();
 }
 
@@ -443,7 +519,8 @@ template <int r, typename T>
 hipError_t launch_ncc_r(const Plan& P, const T* ref, const float* tar_w, const float* zX,
                         const float* isdX, const float* zY, const float* isdY, float* C,
                         int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
-                        int d_first, int d_end, int quad, hipStream_t s) {
+                        int d_first, int d_end, int quad, int pad,
+                        hipStream_t s) {
   int dc = P.ncc_levels;
   if (dc == 0) {
     // automatic: the smallest block that holds every level, at most 64 (a
@@ -455,13 +532,13 @@ hipError_t launch_ncc_r(const Plan& P, const T* ref, const float* tar_w, const f
   switch (dc) {
     case 32:
       return launch_ncc_rdc<r, T, 32>(P, ref, tar_w, zX, isdX, zY, isdY, C, out_w, out_pitch,
-                                      out_slice, anchor, d_first, d_end, quad, s);
+                                      out_slice, anchor, d_first, d_end, quad, pad, s);
     case 64:
       return launch_ncc_rdc<r, T, 64>(P, ref, tar_w, zX, isdX, zY, isdY, C, out_w, out_pitch,
-                                      out_slice, anchor, d_first, d_end, quad, s);
+                                      out_slice, anchor, d_first, d_end, quad, pad, s);
     default:
       return launch_ncc_rdc<r, T, 16>(P, ref, tar_w, zX, isdX, zY, isdY, C, out_w, out_pitch,
-                                      out_slice, anchor, d_first, d_end, quad, s);
+                                      out_slice, anchor, d_first, d_end, quad, pad, s);
   }
 }
 
@@ -469,10 +546,12 @@ template <typename T>
 hipError_t launch_ncc_t(const Plan& P, const T* ref, const float* tar_w, const float* zX,
                         const float* isdX, const float* zY, const float* isdY, float* C,
                         int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
-                        int d_first, int d_end, int quad, hipStream_t s) {
+                        int d_first, int d_end, int quad, int pad,
+                        hipStream_t s) {
 #define NCC_CASE(R_) \
   case R_: return launch_ncc_r<R_, T>(P, ref, tar_w, zX, isdX, zY, isdY, C, out_w, \
-                                      out_pitch, out_slice, anchor, d_first, d_end, quad, s);
+                                      out_pitch, out_slice, anchor, d_first, d_end, quad, pad, \
+                                      s);
   switch (P.r) {
     NCC_CASE(1) NCC_CASE(2) NCC_CASE(3) NCC_CASE(4)
     NCC_CASE(5) NCC_CASE(6) NCC_CASE(7) NCC_CASE(8)
@@ -550,9 +629,13 @@ namespace {
 template <int r, typename T, int DC>
 hipError_t ncc_jobs_rdc(int quad, const NccJob* jobs, const int* first, int n, int blocks,
                         hipStream_t s) {
-  hipError_t e = quad ? ncc_allow_lds<r, T, 1, DC, 1>() : ncc_allow_lds<r, T, 0, DC, 1>();
+  hipError_t e = quad == 2 ? ncc_allow_lds<r, T, 2, DC, 1>()
+                 : quad ? ncc_allow_lds<r, T, 1, DC, 1>() : ncc_allow_lds<r, T, 0, DC, 1>();
   if (e != hipSuccess) return e;
-  if (quad)
+  if (quad == 2)
+    hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 2, DC>), dim3(blocks), dim3(16 * DC),
+                       (NccGeom<r, DC>::lds_bytes), s, jobs, first, n);
+  else if (quad)
     hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 1, DC>), dim3(blocks), dim3(16 * DC),
                        (NccGeom<r, DC>::lds_bytes), s, jobs, first, n);
   else
@@ -650,14 +733,16 @@ hipError_t launch_ncc(const Plan& P, const void* ref, const float* tar_w,
                       const float* zX, const float* isdX, const float* zY,
                       const float* isdY, float* C, int out_w, int64_t out_pitch,
                       int64_t out_slice, int anchor, hipStream_t s, int d_first, int d_end,
-                      int quad) {
+                      int quad, int pad) {
   if (d_end < 0) d_end = P.D;
-  if (quad && (d_first & 3)) return hipErrorInvalidValue;
+  if (quad == 1 && (d_first & 3)) return hipErrorInvalidValue;
+  if (quad == 2 && (d_first & 15 || pad < 0 || (out_pitch & 7) || out_w < out_pitch))
+    return hipErrorInvalidValue;
   if (P.p.dtype == STEREO_U8)
     return launch_ncc_t(P, (const uint8_t*)ref, tar_w, zX, isdX, zY, isdY, C, out_w,
-                        out_pitch, out_slice, anchor, d_first, d_end, quad, s);
+                        out_pitch, out_slice, anchor, d_first, d_end, quad, pad, s);
   return launch_ncc_t(P, (const float*)ref, tar_w, zX, isdX, zY, isdY, C, out_w, out_pitch,
-                      out_slice, anchor, d_first, d_end, quad, s);
+                      out_slice, anchor, d_first, d_end, quad, pad, s);
 }
 
 }  // namespace stereo

@@ -643,13 +643,24 @@ stereo_status stereo_soft_forward(stereo_plan_t plan, const float* ref, const fl
   HIPC(launch_warp(P, tar, tarw, stream), "warp");
   HIPC(launch_block_stats(P, ref, STEREO_F32, P.p.pitch_ref, m.zX, m.isdX, stream), "stats");
   HIPC(launch_block_stats(P, tarw, STEREO_F32, P.W, m.zY, m.isdY, stream), "stats");
-  HIPC(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, cvol, P.W, P.W, (int64_t)HW, 0,
-                  stream, 0, -1, 1), "ncc");
   BilArgs a{};
-  a.C = cvol;                       // float4 quads of levels: [ceil(D/4)][H][W]
-  a.c_slice = (int64_t)HW;
-  a.c_pitch = P.W;
-  a.quad = 1;
+  if (P.agg_engine == 2) {
+    // split-FP16 reference-anchored volume for the FP16-operand matrix cores
+    uint16_t* vR = at<uint16_t>(ws, P.off_cvol);
+    const int64_t plane = 16 * (int64_t)P.H * P.h2_pitch;
+    HIPC(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, reinterpret_cast<float*>(vR),
+                    P.h2_pitch, P.h2_pitch, plane, 0, stream, 0, -1, 2, P.R), "ncc");
+    a.h2 = vR;
+    a.h2_plane = plane;
+    a.h2_pitch = P.h2_pitch;
+  } else {
+    HIPC(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, cvol, P.W, P.W, (int64_t)HW, 0,
+                    stream, 0, -1, 1), "ncc");
+    a.C = cvol;                     // float4 quads of levels: [ceil(D/4)][H][W]
+    a.c_slice = (int64_t)HW;
+    a.c_pitch = P.W;
+    a.quad = 1;
+  }
   a.guide = ref;
   a.guide_dt = STEREO_F32;
   a.guide_pitch = P.p.pitch_ref;

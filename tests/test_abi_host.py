@@ -121,10 +121,10 @@ def test_tuning_keys(lib):
     assert lib.stereo_plan_set_tuning(h, b"ncc_levels", 64) == 0
     assert lib.stereo_plan_get_tuning(h, b"ncc_levels", ctypes.byref(v)) == 0 and v.value == 64
     assert lib.stereo_plan_set_tuning(h, b"ncc_levels", 48) == 1
-    assert lib.stereo_plan_get_tuning(h, b"agg_engine", ctypes.byref(v)) == 0 and v.value == 1
+    assert lib.stereo_plan_get_tuning(h, b"agg_engine", ctypes.byref(v)) == 0 and v.value == 2
     assert lib.stereo_plan_set_tuning(h, b"agg_engine", 0) == 0
     assert lib.stereo_plan_get_tuning(h, b"agg_engine", ctypes.byref(v)) == 0 and v.value == 0
-    assert lib.stereo_plan_set_tuning(h, b"agg_engine", 2) == 1
+    assert lib.stereo_plan_set_tuning(h, b"agg_engine", 3) == 1
     assert lib.stereo_plan_set_tuning(h, b"no_such_key", 8) == 1
     lib.stereo_plan_destroy(h)
 

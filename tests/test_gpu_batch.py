@@ -82,7 +82,7 @@ def test_full_batch_equals_plain_path():
     print(f"[batch] {len(items)} pairs bitwise equal to the plain path", flush=True)
 
 
-@pytest.mark.parametrize("engine", [1, 0], ids=["mfma", "valu"])
+@pytest.mark.parametrize("engine", [2, 1, 0], ids=["mfma16", "mfma", "valu"])
 def test_batch_equals_plain_path(small_batch, engine):
     items = _make(small_batch)
     b = api.Batch(items)

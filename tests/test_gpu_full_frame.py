@@ -60,7 +60,7 @@ def _host(t):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("engine", [1, 0], ids=["mfma", "valu"])
+@pytest.mark.parametrize("engine", [2, 1, 0], ids=["mfma16", "mfma", "valu"])
 @pytest.mark.parametrize("name", ["c2", "c3a", "c3b"])
 def test_full_frame_match(pool, name, engine):
     w, sc, ora = _plain(name, pool)

@@ -76,10 +76,11 @@ def case(name):
     return _cache[name]
 
 
-@pytest.mark.parametrize("engine", [1, 0])
+@pytest.mark.parametrize("engine", [2, 1, 0])
 @pytest.mark.parametrize("name", list(CASES))
 def test_soft_forward(name, engine):
-    """Both aggregation engines (1: matrix cores, 0: vector ALU)."""
+    """Every aggregation engine (2: matrix cores with split-FP16 operands, 1:
+    matrix cores with FP32 operands, 0: vector ALU)."""
     w, sc, g, fwd, bwd = case(name)
     plan = api.Plan.from_workload(w)
     plan.set_tuning("agg_engine", engine)
@@ -217,15 +218,16 @@ def test_full_size_soft_forward_sampled():
     assert abs(gp[0] - fd) < 2e-2 * max(abs(fd), 1e-3), (gp[0], fd)
 
 
-def test_soft_engines_agree_at_full_size():
-    """1280x720 F32 pair, 48 levels, 11x11 aggregation: the matrix-core and the
-    vector-ALU engines sum in different orders; their soft levels and softmax
-    state agree to FP32 rounding at every pixel."""
+@pytest.mark.parametrize("engine", [2, 1])
+def test_soft_engines_agree_at_full_size(engine):
+    """1280x720 F32 pair, 48 levels, 11x11 aggregation: each matrix-core
+    engine and the vector-ALU engine sum in different orders; their soft
+    levels and softmax state agree to FP32 rounding at every pixel."""
     w = workload("c5")
     sc = make_workload_pair(w)
     ref, tar = _dev(sc.ref), _dev(sc.tar)
     out = []
-    for engine in (1, 0):
+    for engine in (engine, 0):
         plan = api.Plan.from_workload(w)
         plan.set_tuning("agg_engine", engine)
         disp, saved = api.soft_forward(plan, ref, tar, w.plane)

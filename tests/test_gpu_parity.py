@@ -216,7 +216,7 @@ def test_bilateral_and_selection(name):
     _check_selection(w, ora, _host(dR), _host(dT), _host(dsub), _host(valid), _host(disp))
 
 
-@pytest.mark.parametrize("engine", [1, 0], ids=["mfma", "valu"])
+@pytest.mark.parametrize("engine", [2, 1, 0], ids=["mfma16", "mfma", "valu"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_fused_match(name, engine):
     """Both aggregation engines of the fused path (matrix cores, vector ALU)."""
@@ -235,7 +235,7 @@ _check_selection = PR.check_selection
 _flat_share_ok = PR.flat_share_ok
 
 
-@pytest.mark.parametrize("engine", [1, 0], ids=["mfma", "valu"])
+@pytest.mark.parametrize("engine", [2, 1, 0], ids=["mfma16", "mfma", "valu"])
 @pytest.mark.parametrize("name", ["c1", "rolled", "f32"])
 def test_tuning_variants_are_bitwise_identical(name, engine):
     """Launch-shape choices never change results: every level chunk gives the
@@ -256,20 +256,22 @@ def test_tuning_variants_are_bitwise_identical(name, engine):
             assert np.array_equal(outs[0][k], o[k], equal_nan=True), k
 
 
-def test_engines_agree_at_full_size():
-    """The two aggregation engines on the headline workload: the same
-    disparities except at near ties (different FP32 summation orders), and
-    sub-pixel values within FP32 rounding of the refinement where they agree."""
+@pytest.mark.parametrize("engine", [2, 1], ids=["mfma16", "mfma"])
+def test_engines_agree_at_full_size(engine):
+    """Each matrix-core engine against the vector-ALU engine on the headline
+    workload: the same disparities except at near ties (different summation
+    orders), and sub-pixel values within rounding of the refinement where
+    they agree."""
     w = workload("c3a")
     sc = make_workload_pair(w)
     ref, tar = _dev(sc.ref), _dev(sc.tar)
     out = {}
-    for engine in (1, 0):
+    for e in (engine, 0):
         plan = api.Plan.from_workload(w)
-        plan.set_tuning("agg_engine", engine)
+        plan.set_tuning("agg_engine", e)
         o = api.match(plan, ref, tar, want_target=True)
-        out[engine] = {k: _host(v) for k, v in o.items()}
-    a, b = out[1], out[0]
+        out[e] = {k: _host(v) for k, v in o.items()}
+    a, b = out[engine], out[0]
     for k in ("dint_R", "dint_T"):
         frac = np.mean(a[k] != b[k])
         print(f"[engines] {k}: {frac:.2e} of pixels differ", flush=True)
