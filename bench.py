@@ -647,6 +647,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=240)
     ap.add_argument("--no-extra", dest="extra", action="store_false")
+    ap.add_argument("--only", choices=("fwd_bwd", "batched"), default=None,
+                    help="run one extra section alone and print its JSON (profiling runs)")
     ap.add_argument("--serial-inputs", action="store_true",
                     help="generate the batch inputs in this process (runs under a profiler)")
     ap.add_argument("--tune", action="append", default=[],
@@ -660,6 +662,13 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.only == "fwd_bwd":
+        print(json.dumps({"fwd_bwd": fwd_bwd(args)}), flush=True)
+        return
+    if args.only == "batched":
+        scenes, _ = batch_scenes(args.serial_inputs)
+        print(json.dumps({"batched": batched(args, scenes)}), flush=True)
+        return
     res = run(args)
     print(json.dumps(res), flush=True)
 

@@ -63,7 +63,9 @@ enum GradRegion {
   GR_SY,                                        // [3][H][W+D-1] target-side sums
   GR_BSY,                                       // [3][HV][WVY] their boxes
   GR_MU,                                        // [2][H][W+2r] block means of X, Y
-  GR_GXV, GR_GYV, GR_GTARFIX, GR_PART_A, GR_PART_B, GR_SCRATCH, GR_COUNT
+  GR_GXV, GR_GYV, GR_GTARFIX, GR_PART_A, GR_PART_B, GR_SCRATCH,
+  GR_GMAX,                                      // max |C'| of the matrix-core backward
+  GR_COUNT
 };
 
 // Float view of a few plan parameters, precomputed on the host.
@@ -137,6 +139,8 @@ struct BilArgs {
   const uint16_t* h2;
   int64_t h2_plane;   // halves per block part (>= 16 H h2_pitch)
   int h2_pitch;       // columns per stored row (a multiple of 8)
+  // backward passes on the split-FP16 matrix cores: max |C'| (float bits)
+  unsigned int* gmax;
 };
 // mode 0: write the normalised aggregated volume; mode 1: fused WTA and
 // sub-pixel refinement (the volume never leaves the chip); mode 2: fused
@@ -147,6 +151,21 @@ struct BilArgs {
 // E out = dC = sum_q w C, and A2), float guides only.
 hipError_t launch_bilateral(const Plan& P, const BilArgs& a, int mode,
                             hipStream_t s);
+
+// Backward of the soft-argmin head on the split-FP16 matrix cores, for one
+// level tile (radius R <= kBwd16MaxR, float guide, d_first a multiple of 16):
+// pass 1 reads the tile's split costs (a.h2) and writes C' = dE / W_p as FP32
+// blocks [ceil(levels/16)][H][ceil(W/4)][16 levels][4 columns] to a.E, with
+// aP, A1, Wp as mode 5 and the max |C'| into *a.gmax (zeroed by the caller
+// before the backward); pass 2 reads the split C' (a.h2) and writes dC planar
+// [levels][H][W] to a.E and A2 as mode 6 (a.cpix: the tile's costs, planar).
+constexpr int kBwd16MaxR = 5;
+hipError_t launch_bilateral_bwd16(const Plan& P, const BilArgs& a, int pass, hipStream_t s);
+// C' blocks -> the split-FP16 volume pass 2 stages (scaled by a power of two
+// from *gmax), levels [0, levels) of the tile.
+hipError_t launch_cprime_split(const float* cblk, const unsigned int* gmax, uint16_t* h2,
+                               int64_t plane, int pitch, int W, int H, int R, int levels,
+                               hipStream_t s);
 
 // Row pitch (halves, a multiple of 8) of the split-FP16 volumes at window
 // radius R for width W: covers the halo columns of every 16-pixel tile.

@@ -1,5 +1,5 @@
 // Aggregation kernels instantiated for window radius R = 3.
-#include "bilateral_mfma16.h"
+#include "bilateral_mfma16_bwd.h"
 
 namespace stereo {
 hipError_t launch_bilateral_r3(const Plan& P, const BilArgs& a, int mode, hipStream_t s) {
@@ -15,5 +15,8 @@ hipError_t launch_bilateral_persistent_r3(int engine, stereo_dtype gdt, int leve
   if (engine == 2) return bilh::launch_queue_r<3>(gdt, p, tiles, n_tiles, counter, n_groups, s);
   if (engine == 1) return bilm::launch_queue_r<3>(gdt, p, tiles, n_tiles, counter, n_groups, s);
   return bil::launch_persistent_r<3>(gdt, levels, p, tiles, n_tiles, counter, n_groups, s);
+}
+hipError_t launch_bwd16_r3(const Plan& P, const BilArgs& a, int pass, hipStream_t s) {
+  return bilh::launch_bwd_args<3>(P, a, pass, s);
 }
 }  // namespace stereo

@@ -434,7 +434,7 @@ fix_to_float_kernel(const unsigned long long* __restrict__ fx, int64_t n, const 
 }
 
 // Several regions cleared by one launch: grid.y picks the region.
-constexpr int kZeroMax = 8;
+constexpr int kZeroMax = 9;
 struct ZeroList {
   float* p[kZeroMax];
   int64_t n[kZeroMax];
@@ -535,6 +535,8 @@ size_t grad_layout(Plan& P, size_t o) {
   for (int i = GR_WP; i <= GR_GTARW; ++i) sz[i] = f4 * HW;
   sz[GR_SUMS] = 3 * f4 * HW;
   for (int i = GR_CT; i <= GR_GCT; ++i) sz[i] = f4 * DT * HW;
+  // the matrix-core backward writes C' in 16-level blocks of column quads
+  sz[GR_GT] = std::max(sz[GR_GT], f4 * ((DT + 15) / 16) * 16 * P.H * (((size_t)P.W + 3) / 4) * 4);
   sz[GR_FA] = f4 * DT * HW;
   sz[GR_BA] = f4 * DT * HV * WVX;
   sz[GR_BS] = 3 * f4 * HV * WVX;
@@ -547,6 +549,7 @@ size_t grad_layout(Plan& P, size_t o) {
   sz[GR_PART_A] = sizeof(double) * 3 * nb;
   sz[GR_PART_B] = sizeof(double) * 3 * nb;
   sz[GR_SCRATCH] = sizeof(double) * 4;
+  sz[GR_GMAX] = sizeof(float);
   for (int i = 0; i < GR_COUNT; ++i) {
     P.g_off[i] = o;
     o = align256(o + sz[i]);
@@ -721,9 +724,9 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
   {
     ZeroList z{};
     float* const reg[kZeroMax] = {aP, A1, A2, SamY, SaX, gXv, gYv,
-                                  reinterpret_cast<float*>(gfix)};
+                                  reinterpret_cast<float*>(gfix), R_(GR_GMAX)};
     const int64_t len[kZeroMax] = {HW, HW, HW, 3 * HW, 2 * HWY, HVWV, (int64_t)HV * WVY,
-                                   2 * HW};
+                                   2 * HW, 1};
     int64_t nmax = 0;
     for (int k = 0; k < kZeroMax; ++k) {
       z.p[k] = reg[k];
@@ -747,12 +750,47 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
   }
 
   const int n = (2 * r + 1) * (2 * r + 1);
+  // the aggregation passes on the split-FP16 matrix cores where they fit
+  // (small radii: two weight operands per lane) and the level tiles start on
+  // 16-level blocks; elsewhere on the vector ALU
+  const bool mc = P.agg_engine == 2 && P.R <= kBwd16MaxR && (D <= DT || DT % 16 == 0);
   for (int d0 = 0; d0 < D; d0 += DT) {
     const int nl = std::min(DT, D - d0);
     // recompute this tile of the cost volume
     HIPC(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, Ct, W, W, HW, 0, stream, d0,
                     d0 + nl), "ncc tile");
     // pass 1: aggregated costs E, the softmax adjoint dE, dE / W_p, aP, A1 (and W_p)
+    if (mc) {
+      // matrix cores: the tile's costs again, split (reference-anchored
+      // blocks), the two passes over split operands, C' re-split between them
+      uint16_t* hC = at<uint16_t>(ws, P.off_cvol);
+      uint16_t* hG = at<uint16_t>(ws, P.off_cvol + P.h2_tar_off);
+      const int64_t hplane = 16 * (int64_t)H * P.h2_pitch;
+      HIPC(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, reinterpret_cast<float*>(hC),
+                      P.h2_pitch, P.h2_pitch, hplane, 0, stream, d0, d0 + nl, 2, P.R),
+           "ncc tile (split)");
+      BilArgs a{};
+      a.h2 = hC; a.h2_plane = hplane; a.h2_pitch = P.h2_pitch;
+      a.guide = ref; a.guide_dt = STEREO_F32; a.guide_pitch = P.p.pitch_ref;
+      a.levels = nl;
+      a.E = Gt;
+      a.sm_m = const_cast<float*>(sm_m);
+      a.sm_logZ = const_cast<float*>(sm_logZ);
+      a.sm_dh = const_cast<float*>(sm_dh);
+      a.gD = grad_disp;
+      a.aP = aP; a.A1 = A1; a.A2 = A2;
+      a.Wp = d0 == 0 ? Wp : nullptr;
+      a.d_first = d0;
+      a.gmax = reinterpret_cast<unsigned int*>(R_(GR_GMAX));
+      a.plane[0] = plane[0]; a.plane[1] = plane[1]; a.plane[2] = plane[2];
+      HIPC(launch_bilateral_bwd16(P, a, 1, stream), "aggregation + softmax adjoint");
+      HIPC(launch_cprime_split(Gt, a.gmax, hG, hplane, P.h2_pitch, W, H, P.R, nl, stream),
+           "split of dE / W");
+      a.h2 = hG;
+      a.E = gCt;
+      a.cpix = Ct;
+      HIPC(launch_bilateral_bwd16(P, a, 2, stream), "aggregation adjoint");
+    } else {
     BilArgs a{};
     a.C = Ct; a.c_slice = HW; a.c_pitch = W;
     a.guide = ref; a.guide_dt = STEREO_F32; a.guide_pitch = P.p.pitch_ref;
@@ -772,6 +810,7 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
     a.E = gCt;
     a.cpix = Ct;
     HIPC(launch_bilateral(P, a, 6, stream), "aggregation adjoint");
+    }
     LAUNCH("ncc adjoint coefficients", ncc_coef_kernel, rows, dim3(kT), 0, stream, Ct, gCt,
            muX, m.isdX, muY, m.isdY, W, H, r, d0, nl, 1.0f / (float)n, Fa, Sb, SbmX, SamY);
     LAUNCH("ncc adjoint target sums", ncc_shear_kernel, dim3((WY + kT - 1) / kT, H), dim3(kT), 0,

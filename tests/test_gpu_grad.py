@@ -92,10 +92,14 @@ def test_soft_forward(name, engine):
     assert np.max(np.abs(saved[1] - fwd["logZ"]) / np.maximum(np.abs(fwd["logZ"]), 1)) < 1e-4
 
 
+@pytest.mark.parametrize("engine", [2, 0], ids=["mfma16", "valu"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_backward_matches_fp64_adjoint(name):
+def test_backward_matches_fp64_adjoint(name, engine):
+    """engine 2: the aggregation passes on the split-FP16 matrix cores (R <= 5;
+    the R = 8 case takes the vector ALU on both); engine 0: the vector ALU."""
     w, sc, g, fwd, bwd = case(name)
     plan = api.Plan.from_workload(w)
+    plan.set_tuning("agg_engine", engine)
     ref, tar = _dev(sc.ref), _dev(sc.tar)
     disp, saved = api.soft_forward(plan, ref, tar, w.plane)
     g_ref, g_tar, g_plane = api.backward(plan, ref, tar, w.plane, saved, _dev(g))
@@ -107,7 +111,8 @@ def test_backward_matches_fp64_adjoint(name):
         assert abs(gp[k] - o_plane[k]) <= 1e-3 * max(abs(o_plane[k]), 1e-6 * np.abs(o_plane).max()), (k, gp, o_plane)
 
 
-def test_flat_patch_has_no_ncc_gradient():
+@pytest.mark.parametrize("engine", [2, 0], ids=["mfma16", "valu"])
+def test_flat_patch_has_no_ncc_gradient(engine):
     """Inside an exactly uniform reference patch, deeper than 2r (every block
     reading the pixel is uniform: cost 1, no NCC gradient) and deeper than R
     (every guide difference is zero: no range-weight gradient), the
@@ -115,6 +120,7 @@ def test_flat_patch_has_no_ncc_gradient():
     w, sc, g, fwd, bwd = case("flat")
     c = CASES["flat"]
     plan = api.Plan.from_workload(w)
+    plan.set_tuning("agg_engine", engine)
     ref, tar = _dev(sc.ref), _dev(sc.tar)
     disp, saved = api.soft_forward(plan, ref, tar, w.plane)
     g_ref, _, _ = api.backward(plan, ref, tar, w.plane, saved, _dev(g))
