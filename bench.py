@@ -61,10 +61,11 @@ def _sha(path):
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def _traffic(kernel_src, launches_bytes_key):
+def _traffic(kernel_src, launches_bytes_key,
+             name="traffic_bilateral_road1280x720_d64_persp.json"):
     """HBM bytes per launch from committed rocprofv3 counter summaries, only
     if the kernel source is unchanged since they were taken."""
-    f = os.path.join(ROOT, "profiles", "traffic_bilateral_road1280x720_d64_persp.json")
+    f = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(f):
         return None
     d = json.load(open(f))
@@ -277,13 +278,51 @@ def batched(args, scenes):
     torch.cuda.synchronize()
     t_p = e[2].elapsed_time(e[3]) / n
     same = all(torch.equal(o["dint_R"], p["dint_R"]) for o, p in zip(b.outputs, outs))
+    # the persistent aggregation launches (every group), timed live around a
+    # plain submission of the same batch
+    import ctypes
+    lib = api._lib.load()
+    agg = []
+    for _ in range(n):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        for x in ev:
+            x.record()                   # materialise the underlying event objects
+        evp = (ctypes.c_void_p * 2)(*[x.cuda_event for x in ev])
+        api.check(lib.stereo_submit_batch_profiled(b._h, api._p(b.ws), b.workspace_bytes, evp,
+                                                   api._stream()))
+        agg.append(ev)
+    torch.cuda.synchronize()
+    agg_ms = sum(e[0].elapsed_time(e[1]) for e in agg) / n
+    flops = sum(2 * 2.0 * (2 * w.bil_radius + 1) ** 2 * w.width * w.height * w.num_disp for w in ws)
+    achieved = flops / (agg_ms / 1e3) / 1e12
+    engine = b.get_tuning("agg_engine")
+    if engine == 2:
+        issued = sum(2 * 3 * 2.0 * mfma16_k(w.bil_radius) * w.width * w.height * w.num_disp
+                     for w in ws)
+        src = os.path.join(ROOT, "paper_1904_06017_amd", "csrc", "bilateral_mfma16.h")
+        roof = dict(kernel="agg_mfma16_kernel, queued (all groups of the batch)", bound="mfma",
+                    achieved=round(achieved, 2), peak=MI355X_FP16_MFMA_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / MI355X_FP16_MFMA_TFLOPS, 4),
+                    issued_frac=round(issued / (agg_ms / 1e3) / 1e12 / MI355X_FP16_MFMA_TFLOPS, 4),
+                    frac_vs_fp32_peak=round(achieved / MI355X_FP32_MFMA_TFLOPS, 4),
+                    flops_per_batch=flops, issued_flops_per_batch=issued,
+                    aggregation_ms=round(agg_ms, 3),
+                    traffic=_traffic(src, "hbm_bytes_per_batch",
+                                     "traffic_batch_mixed64.json"))
+    else:
+        roof = dict(kernel="queued aggregation (all groups of the batch)",
+                    bound="mfma" if engine == 1 else "alu", achieved=round(achieved, 2),
+                    peak=MI355X_FP32_MFMA_TFLOPS if engine == 1 else round(MI355X_FP32_VALU_TFLOPS, 1),
+                    unit="TFLOP/s", aggregation_ms=round(agg_ms, 3), flops_per_batch=flops,
+                    traffic=None)
+        roof["frac"] = round(achieved / roof["peak"], 4)
     return dict(pairs=len(ws), elements=el, batch_ms=round(t_b, 3),
                 batch_gpd_s=round(el / (t_b / 1e3) / 1e9, 3), per_pair_ms=round(t_p, 3),
                 per_pair_gpd_s=round(el / (t_p / 1e3) / 1e9, 3),
                 speedup_vs_per_pair=round(t_p / t_b, 3), equal_to_per_pair=bool(same),
                 tuning={k: b.get_tuning(k) for k in ("agg_engine", "wg_per_cu", "agg_levels_u8",
                                                      "agg_levels_f32")},
-                autotune_best_ms=round(tuned_ms, 3))
+                autotune_best_ms=round(tuned_ms, 3), roofline=roof)
 
 
 def run(args):
@@ -597,7 +636,11 @@ def copy_calibration(mib):
 
 def fwd_bwd(args):
     """Differentiable form at 1280x720 FP32, 48 levels: soft-argmin forward,
-    photometric L1, its backward and the backward of the soft head."""
+    photometric L1, its backward and the backward of the soft head.  The
+    backward's two aggregation passes are timed live with events on the
+    stream they run on (the dominant kernels: roofline)."""
+    import ctypes
+
     import torch
 
     from paper_1904_06017_amd import api
@@ -608,17 +651,33 @@ def fwd_bwd(args):
     dev = torch.device("cuda:0")
     ref = torch.from_numpy(sc.ref).to(dev)
     tar = torch.from_numpy(sc.tar).to(dev)
+    H, W = w.height, w.width
+    lib = api._lib.load()
+    g_ref = torch.empty((H, W), dtype=torch.float32, device=dev)
+    g_tar = torch.empty_like(g_ref)
+    g_plane = torch.empty(3, dtype=torch.float64, device=dev)
+    ws = plan.workspace(dev)
 
-    def step():
+    def step(ev=None):
         disp, saved = api.soft_forward(plan, ref, tar, w.plane)
         loss = api.photometric_l1(plan, ref, tar, disp)
-        g_ref, g_tar, g_disp = api.photometric_l1_bwd(plan, ref, tar, disp, 1.0)
-        return api.backward(plan, ref, tar, w.plane, saved, g_disp), loss
+        _, _, g_disp = api.photometric_l1_bwd(plan, ref, tar, disp, 1.0)
+        evp = None if ev is None else (ctypes.c_void_p * 6)(*[e.cuda_event for e in ev])
+        api.check(lib.stereo_backward_profiled(
+            plan.handle, api._p(ref), api._p(tar), api._plane3(w.plane), api._p(saved),
+            api._p(g_disp), api._p(g_ref), api._p(g_tar), api._p(g_plane), api._p(ws),
+            plan.workspace_bytes, evp, api._stream()))
+        return loss
 
     for _ in range(2):
         step()
     torch.cuda.synchronize()
     n = max(3, args.steps // 10)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(n)]
+    for e in evs:
+        for x in e:
+            x.record()
+    torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
     c = torch.cuda.Event(enable_timing=True)
@@ -626,17 +685,47 @@ def fwd_bwd(args):
     for _ in range(n):
         api.soft_forward(plan, ref, tar, w.plane)
     b.record()
-    for _ in range(n):
-        step()
+    for k in range(n):
+        step(evs[k])
     c.record()
     torch.cuda.synchronize()
     f_ms = a.elapsed_time(b) / n
     fb_ms = b.elapsed_time(c) / n
+    st = lambda i, j: sum(evs[k][i].elapsed_time(evs[k][j]) for k in range(n)) / n
+    p1, p2, bwd = st(1, 2), st(3, 4), st(0, 5)
     el = w.width * w.height * w.num_disp
+    engine = plan.get_tuning("agg_engine")
+    R = w.bil_radius
+    taps = (2 * R + 1) ** 2
+    # each pass: two weighted window sums per pixel-level (the weights, and the
+    # weights times the guide difference), 2 (2R+1)^2 flops each
+    flops = 2 * 2.0 * taps * el
+    dom_ms = max(p1, p2)
+    achieved = flops / (dom_ms / 1e3) / 1e12
+    if engine == 2 and R <= 5:
+        issued = 2 * 3 * 2.0 * mfma16_k(R) * el
+        src = os.path.join(ROOT, "paper_1904_06017_amd", "csrc", "bilateral_mfma16_bwd.h")
+        roof = dict(kernel="agg_mfma16_bwd_kernel (slower of the two passes)", bound="mfma",
+                    achieved=round(achieved, 2), peak=MI355X_FP16_MFMA_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / MI355X_FP16_MFMA_TFLOPS, 4),
+                    issued_tflops=round(issued / (dom_ms / 1e3) / 1e12, 1),
+                    issued_frac=round(issued / (dom_ms / 1e3) / 1e12 / MI355X_FP16_MFMA_TFLOPS, 4),
+                    frac_vs_fp32_peak=round(achieved / MI355X_FP32_MFMA_TFLOPS, 4),
+                    flops_per_launch=flops, issued_flops_per_launch=issued,
+                    avg_launch_ms=round(dom_ms, 4),
+                    traffic=_traffic(src, "pass1_bytes" if p1 >= p2 else "pass2_bytes",
+                                     "traffic_bwd_road1280x720_f32_d48_soft.json"))
+    else:
+        src = os.path.join(ROOT, "paper_1904_06017_amd", "csrc", "bilateral_impl.h")
+        roof = dict(kernel="bilateral_kernel modes 5/6 (slower of the two passes)", bound="alu",
+                    achieved=round(achieved, 2), peak=round(MI355X_FP32_VALU_TFLOPS, 1),
+                    unit="TFLOP/s", frac=round(achieved / MI355X_FP32_VALU_TFLOPS, 4),
+                    flops_per_launch=flops, avg_launch_ms=round(dom_ms, 4), traffic=None)
     return dict(workload=w.name, num_disp=w.num_disp, fwd_ms=round(f_ms, 4),
                 fwd_gpd_s=round(el / (f_ms / 1e3) / 1e9, 3), fwd_bwd_ms=round(fb_ms, 4),
                 fwd_bwd_gpd_s=round(el / (fb_ms / 1e3) / 1e9, 3),
-                grad_levels=plan.get_tuning("grad_levels"))
+                bwd_ms=round(bwd, 4), bwd_pass1_ms=round(p1, 4), bwd_pass2_ms=round(p2, 4),
+                grad_levels=plan.get_tuning("grad_levels"), agg_engine=engine, roofline=roof)
 
 
 def main():

@@ -324,6 +324,11 @@ stereo_status stereo_batch_get_tuning(stereo_batch_t b, const char* key, int32_t
  * workspace uploads the per-pair descriptors and synchronises the stream. */
 stereo_status stereo_submit_batch(stereo_batch_t b, void* ws, size_t ws_bytes,
                                   hipStream_t stream);
+/* The same, recording caller-owned events on `stream` around the persistent
+ * aggregation launches (Eqs. 10-11 with the fused selection of Eq. 13, all
+ * groups): ev[0] before the first, ev[1] after the last.  For profiling. */
+stereo_status stereo_submit_batch_profiled(stereo_batch_t b, void* ws, size_t ws_bytes,
+                                           hipEvent_t* ev, hipStream_t stream);
 /* Upload the descriptors (synchronising `stream`) and capture the batch into a
  * graph bound to `ws`; stereo_batch_launch replays it on any stream. */
 stereo_status stereo_batch_instantiate(stereo_batch_t b, void* ws, size_t ws_bytes,
@@ -375,6 +380,18 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
                               const float* grad_disp, float* grad_ref, float* grad_tar,
                               double* grad_plane, void* ws, size_t ws_bytes,
                               hipStream_t stream);
+/* The same, recording caller-owned events on `stream` (for profiling;
+ * results identical): ev[0] start, ev[1] before the first level tile's first
+ * aggregation pass (Eq. 11 and the softmax adjoint), ev[2] after it, ev[3]
+ * before its second pass (the adjoint of Eq. 11's sum), ev[4] after it, ev[5]
+ * end.  With one level tile (D <= 64 by default) [1, 2] and [3, 4] time the
+ * two aggregation passes of the whole backward. */
+#define STEREO_BACKWARD_EVENTS 6
+stereo_status stereo_backward_profiled(stereo_plan_t plan, const float* ref, const float* tar,
+                                       const double plane[3], const float* saved,
+                                       const float* grad_disp, float* grad_ref, float* grad_tar,
+                                       double* grad_plane, void* ws, size_t ws_bytes,
+                                       hipEvent_t* ev, hipStream_t stream);
 
 /* Photometric L1 loss L = mean_p |ref(p) - lerp(tar, v, u - disp_soft(p))|
  * (row lerp, clamped), written to *loss_dev (device double).  The _bwd call

@@ -102,6 +102,9 @@ SIGNATURES = {
     "stereo_backward": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_double), c_void_p,
                                 c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                 c_void_p]),
+    "stereo_backward_profiled": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_double),
+                                         c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                         c_void_p, c_size_t, c_void_p, c_void_p]),
     "stereo_photometric_l1": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                       c_void_p, c_size_t, c_void_p]),
     "stereo_photometric_l1_bwd": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double,
@@ -112,6 +115,7 @@ SIGNATURES = {
     "stereo_batch_set_tuning": (c_int, [c_void_p, c_char_p, c_int32]),
     "stereo_batch_get_tuning": (c_int, [c_void_p, c_char_p, POINTER(c_int32)]),
     "stereo_submit_batch": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "stereo_submit_batch_profiled": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
     "stereo_batch_instantiate": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "stereo_batch_launch": (c_int, [c_void_p, c_void_p]),
     "stereo_batch_destroy": (c_int, [c_void_p]),

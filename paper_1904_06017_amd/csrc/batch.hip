@@ -88,6 +88,8 @@ T* at(void* ws, size_t off) {
 // covers the extended columns (anchor 0 only), the split-FP16 volumes the
 // stored rows of both anchors (the target-anchored one when the pair has an
 // LR check).
+constexpr int kBandTiles = 4;   // tile columns per band of the matrix-core tile order
+
 void ncc_blocks(stereo_batch_s& b) {
   for (JobList& L : b.lists) {
     if (L.kind != JK_NCC) continue;
@@ -134,8 +136,12 @@ void build_layout(stereo_batch_s& b) {
       const int gi = find_group(P.R, g);
       for (int y = 0; y < P.H; y += kBilTileH)
         for (int x = 0; x < P.W; x += kBilTileW) per[gi].push_back({P.D, i, vol, x, y});
-      for (int y = 0; y < P.H; y += kMfmaTileH)
-        for (int x = 0; x < P.W; x += kMfmaTileW) per_m[gi].push_back({P.D, i, vol, x, y});
+      // matrix-core tiles in bands of kBandTiles tile columns walked row by
+      // row: a run of the list is a 2-D patch of the image (shared halos)
+      for (int xb = 0; xb < P.W; xb += kBandTiles * kMfmaTileW)
+        for (int y = 0; y < P.H; y += kMfmaTileH)
+          for (int x = xb; x < std::min(P.W, xb + kBandTiles * kMfmaTileW); x += kMfmaTileW)
+            per_m[gi].push_back({P.D, i, vol, x, y});
     }
   }
   auto table = [&](std::vector<T>& src, std::vector<int>& tl, size_t& off) {
@@ -321,7 +327,7 @@ stereo_status bind(stereo_batch_s& b, void* ws, size_t bytes, hipStream_t s) {
   return STEREO_OK;
 }
 
-stereo_status enqueue(stereo_batch_s& b, hipStream_t s) {
+stereo_status enqueue(stereo_batch_s& b, hipStream_t s, hipEvent_t* ev = nullptr) {
   void* ws = b.bound_ws;
   BREQ(ws, "batch not bound to a workspace");
   auto run_list = [&](const JobList& L) -> stereo_status {
@@ -362,6 +368,7 @@ stereo_status enqueue(stereo_batch_s& b, hipStream_t s) {
   hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, ctr, ng);
   BHIP(hipGetLastError(), "zero counters");
   const void* desc = at<char>(ws, b.desc_off);
+  if (ev) BHIP(hipEventRecord(ev[0], s), "event record");
   for (int g = 0; g < ng; ++g) {
     const Group& G = b.groups[g];
     if (b.engine >= 1) {                 // one workgroup per CU holds the whole LDS
@@ -377,6 +384,7 @@ stereo_status enqueue(stereo_batch_s& b, hipStream_t s) {
                                        ctr + g, groups, s), "batch aggregation");
     }
   }
+  if (ev) BHIP(hipEventRecord(ev[1], s), "event record");
   for (const JobList& L : b.lists)
     if (L.kind == JK_LR) {
       stereo_status st = run_list(L);
@@ -467,6 +475,11 @@ stereo_status stereo_batch_get_tuning(stereo_batch_t b, const char* key, int32_t
 
 stereo_status stereo_submit_batch(stereo_batch_t b, void* ws, size_t ws_bytes,
                                   hipStream_t stream) {
+  return stereo_submit_batch_profiled(b, ws, ws_bytes, nullptr, stream);
+}
+
+stereo_status stereo_submit_batch_profiled(stereo_batch_t b, void* ws, size_t ws_bytes,
+                                           hipEvent_t* ev, hipStream_t stream) {
   BREQ(b, "batch is NULL");
   if (b->cu_count == 0) {
     int dev = 0;
@@ -476,7 +489,7 @@ stereo_status stereo_submit_batch(stereo_batch_t b, void* ws, size_t ws_bytes,
   }
   stereo_status s = bind(*b, ws, ws_bytes, stream);
   if (s != STEREO_OK) return s;
-  return enqueue(*b, stream);
+  return enqueue(*b, stream, ev);
 }
 
 stereo_status stereo_batch_instantiate(stereo_batch_t b, void* ws, size_t ws_bytes,

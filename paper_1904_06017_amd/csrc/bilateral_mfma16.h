@@ -344,9 +344,8 @@ agg_mfma16_kernel(View one, const BilPair* __restrict__ pairs, const int* __rest
   }
 
   // tiles of this workgroup.  QUEUE = 1: (pair, x0, y0) triples of a list
-  // sorted longest first, dealt round-robin (workgroup b takes entries b,
-  // b + G, b + 2G, ...), so that every workgroup's share costs nearly the
-  // same.  A shared counter would balance at run time, but an atomic that
+  // sorted longest first, dealt one per workgroup and round (below), so that
+  // every workgroup's share costs nearly the same.  A shared counter would balance at run time, but an atomic that
   // returns its value waits behind the direct-to-LDS copies in flight and
   // stalls the whole workgroup once per tile.  QUEUE = 0, the tiles of one
   // pair: XCD x walks the tile columns of band x row by row.
@@ -363,6 +362,16 @@ agg_mfma16_kernel(View one, const BilPair* __restrict__ pairs, const int* __rest
     }
   }
   auto arith_tile = [&](int k) -> int {
+    if (QUEUE) {
+      // round k of G workgroups covers entries [k G, (k + 1) G); workgroup b
+      // (XCD b % 8) takes entry k G + (b % 8) G / 8 + b / 8, so that each XCD
+      // works on a contiguous run of the list: the host orders a pair's tiles
+      // in bands of a few tile columns walked row by row, so a run is a 2-D
+      // patch of tiles whose halos meet in that XCD's L2
+      const int G = (int)gridDim.x;
+      if (G % 8 == 0) return k * G + ((int)blockIdx.x % 8) * (G / 8) + (int)blockIdx.x / 8;
+      return (int)blockIdx.x + G * k;
+    }
     if (per) {
       const int idx = (int)blockIdx.x / 8 + per * k;
       if (idx >= nb) return n1;

@@ -18,8 +18,10 @@
 // Both operands are split (x = x_hi + x_lo, three FP16 products per term,
 // FP32 accumulation), so the sums are as accurate as FP32 products; the
 // weights carry the 2^12 scale of the forward kernel and C' a power-of-two
-// scale S chosen from max |C'| (the gradient's magnitude is arbitrary), both
-// removed exactly at the end.  Results sit in the matrix-core output layout
+// scale S (the gradient's magnitude is arbitrary) chosen from a bound on
+// |C'|: P <= 1, |d - dh| <= D - 1 and W_p >= 1 (the pixel's own weight) give
+// |C'| <= max |g'| |1 - c1| (D - 1) / T; both scales are removed exactly at
+// the end.  Pass 1 writes C' in the split layout pass 2 stages.  Results sit in the matrix-core output layout
 // (lane: level, block row, four columns), so the epilogues need no LDS: the
 // per-pixel sums over levels are reduced across the 16 level lanes once per
 // tile.
@@ -33,10 +35,10 @@ namespace bilh {
 // input volume (v.D = levels of the tile) and the FP32 guide.
 struct BView {
   View v;
-  float* out;             // pass 1: C' in FP32 blocks [ceil(D/16)][H][ceil(W/4)][16][4]
-                          // pass 2: dC planar [D][H][W]
+  float* out;             // pass 2: dC planar [D][H][W]
+  uint16_t* h2out;        // pass 1: C' S, split-FP16 volume (pitch and plane of v)
   const float* cpix;      // pass 2: C planar [D][H][W]
-  unsigned int* gmax;     // pass 1: atomic max of |C'| (float bits); pass 2: read
+  const unsigned int* gmax;  // max |g'| over the image (float bits), for the scale S
   const float* sm_m;
   const float* sm_logZ;
   const float* sm_dh;
@@ -47,10 +49,11 @@ struct BView {
   float* Wp;              // pass 1, nullable: sum_q w(p, q)
   float invT, one_minus_c1;
   int d_first;            // level of the tile's first slice
+  int d_all;              // levels of the whole range (the bound on |d - dh|)
 };
 
-// Power-of-two scale that puts max |C'| in [2^13, 2^14): FP16 keeps its
-// relative precision for every value above 2^-11 of the largest.
+// Power-of-two scale that puts a bound m on |C'| in [2^13, 2^14) (bits: m
+// as a float): FP16 keeps its range for every value up to the bound.
 __host__ __device__ inline float cprime_scale(unsigned int bits) {
   const int ex = (int)((bits >> 23) & 0xFF);
   if (ex == 0xFF || bits == 0) return 1.0f;          // non-finite or zero: no scaling
@@ -167,10 +170,11 @@ __global__ void __launch_bounds__(kThreads, 1) agg_mfma16_bwd_kernel(BView b) {
 
   const int nl = one.D;
   const int passes = (nl + 15) / 16;
-  const int nqx = (one.W + 3) >> 2;
   // C' scale (pass 2: removed from both sums with the weights' 2^12)
-  const float unscale =
-      PASS == 2 ? 1.0f / (4096.0f * cprime_scale(*b.gmax)) : 1.0f / 4096.0f;
+  const float bound = __uint_as_float(*b.gmax) * fabsf(b.one_minus_c1) * b.invT *
+                      (float)(b.d_all > 1 ? b.d_all - 1 : 1);
+  const float cscale = cprime_scale(__float_as_uint(bound));
+  const float unscale = PASS == 2 ? 1.0f / (4096.0f * cscale) : 1.0f / 4096.0f;
   const float inv_kr = 1.0f / sqrtf(one.kr2);
 
   int cur = arith_tile(0);
@@ -186,7 +190,6 @@ __global__ void __launch_bounds__(kThreads, 1) agg_mfma16_bwd_kernel(BView b) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
-  float lmax = 0.0f;
   int par = 0, gpar = 0, gpass = 0;
   for (int k = 0;; ++k) {
     int x0, y0;
@@ -276,13 +279,27 @@ __global__ void __launch_bounds__(kThreads, 1) agg_mfma16_bwd_kernel(BView b) {
     // last): issued before the copies, they have a pass to complete before
     // the wait at its end instead of holding it up
     float ov[4] = {0.f, 0.f, 0.f, 0.f};
-    int oaddr = -1;                               // pass 1: float4 offset into the C' blocks
+    int oaddr = -1;                               // pass 1: the lane's (level, row) in C' S
     int opass = -1;                               // pass 2: level block held in tout
     int obuf_sel = 0;                             //   and which of the two
     auto flush = [&]() {
       if constexpr (PASS == 1) {
-        if (oaddr >= 0)
-          reinterpret_cast<float4*>(b.out)[oaddr] = make_float4(ov[0], ov[1], ov[2], ov[3]);
+        // level li of stored columns x + R (x = px0 + v), both halves; a
+        // column quad of the layout straddles two of the block's columns
+        // unless R is a multiple of 4, so the halves go out one by one
+        if (oaddr >= 0) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            if (px0 + v < one.W) {
+              const int sc = px0 + v + R;
+              const int o = oaddr + 64 * (sc >> 2) + (sc & 3);
+              const _Float16 hi = (_Float16)ov[v];
+              const _Float16 lo = (_Float16)(ov[v] - (float)hi);
+              b.h2out[o] = __builtin_bit_cast(uint16_t, hi);
+              b.h2out[o + (int)one.plane] = __builtin_bit_cast(uint16_t, lo);
+            }
+          }
+        }
       } else {
         if (opass >= 0) {
           const float* to = tout + obuf_sel * kTileBlk;
@@ -377,7 +394,6 @@ __global__ void __launch_bounds__(kThreads, 1) agg_mfma16_bwd_kernel(BView b) {
       float ca[4], cb2[4];
       if constexpr (PASS == 1) {
         const float gscale = b.one_minus_c1 * (-b.invT);
-        float cmax = 0.0f;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const bool in = dv && rowin && px0 + v < one.W;
@@ -387,17 +403,13 @@ __global__ void __launch_bounds__(kThreads, 1) agg_mfma16_bwd_kernel(BView b) {
               fmaf(-e, b.invT, -(sc[so + v] + sc[16 + so + v])) * 1.4426950408889634f);
           const float dE =
               in ? sc[32 + so + v] * gscale * P * ((float)(b.d_first + d) - sc[48 + so + v]) : 0.0f;
-          ov[v] = dE * rinv * 4096.0f;              // dE / W_p (rinv carries the 2^-12)
+          ov[v] = dE * rinv * (4096.0f * cscale);   // S dE / W_p (rinv carries the 2^-12)
           ca[v] = dE * e;
           cb2[v] = dE * ag[v];
-          cmax = fmaxf(cmax, fabsf(ov[v]));
         }
-        // the wave's largest |C'| so far, kept as one scalar
-#pragma unroll
-        for (int m = 1; m < 64; m <<= 1) cmax = fmaxf(cmax, __shfl_xor(cmax, m));
-        lmax = fmaxf(lmax, __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                                         __builtin_bit_cast(int, cmax))));
-        oaddr = rowin && px0 < one.W ? (int)(((p * one.H + py) * nqx + (px0 >> 2)) * 16 + li) : -1;
+        // offsets below 2^31: at most 64 levels (4 blocks) of one tile
+        oaddr = rowin && px0 < one.W ? (int)((2 * p) * one.plane) + py * 16 * one.pitch + 4 * li
+                                     : -1;
       } else {
         // the costs at (level li, block row lk, columns v); the outputs into
         // the tile's output block at (level li, tile row 4 by + lk, columns 4 bx + v)
@@ -468,10 +480,6 @@ __global__ void __launch_bounds__(kThreads, 1) agg_mfma16_bwd_kernel(BView b) {
     cur = nxt;
     gpar ^= 1;
   }
-  if constexpr (PASS == 1) {
-    // largest |C'| of the launch, for the scale of pass 2's operand
-    if (lane == 0 && lmax > 0.0f) atomicMax(b.gmax, __float_as_uint(lmax));
-  }
 }
 
 inline BView make_bview(const bil::BilPair& bp, const BilArgs& a) {
@@ -480,6 +488,7 @@ inline BView make_bview(const bil::BilPair& bp, const BilArgs& a) {
   b.out = a.E;
   b.cpix = a.cpix;
   b.gmax = a.gmax;
+  b.h2out = a.h2_out;
   b.sm_m = a.sm_m;
   b.sm_logZ = a.sm_logZ;
   b.sm_dh = a.sm_dh;
@@ -517,10 +526,11 @@ hipError_t launch_bwd_pass(const BView& b, hipStream_t s) {
 template <int R>
 hipError_t launch_bwd_args(const Plan& P, const BilArgs& a, int pass, hipStream_t s) {
   const bil::BilPair bp = bil::make_pair(P, a);
-  if (!a.h2 || a.h2_pitch < h2_pitch_for<R>(bp.W) || (a.h2_pitch & 7) || !a.gmax || !a.E ||
-      (pass == 2 && !a.cpix))
+  if (!a.h2 || a.h2_pitch < h2_pitch_for<R>(bp.W) || (a.h2_pitch & 7) || !a.gmax ||
+      (pass == 1 && !a.h2_out) || (pass == 2 && (!a.cpix || !a.E)))
     return hipErrorInvalidValue;
-  const BView b = make_bview(bp, a);
+  BView b = make_bview(bp, a);
+  b.d_all = P.D;
   return pass == 1 ? launch_bwd_pass<R, 1>(b, s) : launch_bwd_pass<R, 2>(b, s);
 }
 

@@ -98,11 +98,13 @@ hipError_t launch_block_stats(const Plan& P, const void* img, stereo_dtype dt,
 // split-FP16 volume of the anchor (see BilArgs::h2), out_pitch = stored
 // columns (a multiple of 8), out_slice = 16 H out_pitch, out_w >= out_pitch,
 // pad = column shift (the window radius R), d_first a multiple of 16.
+// quad = 3 (FP32 images): both the split-FP16 volume in C (as quad 2) and
+// the planar FP32 volume [levels][H][W] in C2, from one pass.
 hipError_t launch_ncc(const Plan& P, const void* ref, const float* tar_w,
                       const float* zX, const float* isdX, const float* zY,
                       const float* isdY, float* C, int out_w, int64_t out_pitch,
                       int64_t out_slice, int anchor, hipStream_t s, int d_first = 0,
-                      int d_end = -1, int quad = 0, int pad = 0);
+                      int d_end = -1, int quad = 0, int pad = 0, float* C2 = nullptr);
 
 struct BilArgs {
   const float* C;     // planar: C[d * c_slice + y * c_pitch + x + d*shift]
@@ -139,8 +141,10 @@ struct BilArgs {
   const uint16_t* h2;
   int64_t h2_plane;   // halves per block part (>= 16 H h2_pitch)
   int h2_pitch;       // columns per stored row (a multiple of 8)
-  // backward passes on the split-FP16 matrix cores: max |C'| (float bits)
-  unsigned int* gmax;
+  // backward passes on the split-FP16 matrix cores: max |g'| (float bits),
+  // and pass 1's output volume (C' scaled, split; pitch and plane of h2)
+  const unsigned int* gmax;
+  uint16_t* h2_out;
 };
 // mode 0: write the normalised aggregated volume; mode 1: fused WTA and
 // sub-pixel refinement (the volume never leaves the chip); mode 2: fused
@@ -154,18 +158,19 @@ hipError_t launch_bilateral(const Plan& P, const BilArgs& a, int mode,
 
 // Backward of the soft-argmin head on the split-FP16 matrix cores, for one
 // level tile (radius R <= kBwd16MaxR, float guide, d_first a multiple of 16):
-// pass 1 reads the tile's split costs (a.h2) and writes C' = dE / W_p as FP32
-// blocks [ceil(levels/16)][H][ceil(W/4)][16 levels][4 columns] to a.E, with
-// aP, A1, Wp as mode 5 and the max |C'| into *a.gmax (zeroed by the caller
-// before the backward); pass 2 reads the split C' (a.h2) and writes dC planar
+// pass 1 reads the tile's split costs (a.h2) and writes C' = dE / W_p, times
+// a power of two set by the bound max |g'| |1 - c1| (D - 1) / T (*a.gmax =
+// max |g'| as float bits), split into a.h2_out (same layout), with aP, A1,
+// Wp as mode 5; pass 2 reads that volume (a.h2) and writes dC planar
 // [levels][H][W] to a.E and A2 as mode 6 (a.cpix: the tile's costs, planar).
+// The stored columns of a.h2_out outside the image are not written: zero
+// them first (launch_h2_pad_zero).
 constexpr int kBwd16MaxR = 5;
 hipError_t launch_bilateral_bwd16(const Plan& P, const BilArgs& a, int pass, hipStream_t s);
-// C' blocks -> the split-FP16 volume pass 2 stages (scaled by a power of two
-// from *gmax), levels [0, levels) of the tile.
-hipError_t launch_cprime_split(const float* cblk, const unsigned int* gmax, uint16_t* h2,
-                               int64_t plane, int pitch, int W, int H, int R, int levels,
-                               hipStream_t s);
+// Zeros in the stored columns outside [0, W) (all levels, both halves) of
+// the first nblk 16-level blocks of a split-FP16 volume at radius R.
+hipError_t launch_h2_pad_zero(uint16_t* h2, int64_t plane, int pitch, int W, int H, int R,
+                              int nblk, hipStream_t s);
 
 // Row pitch (halves, a multiple of 8) of the split-FP16 volumes at window
 // radius R for width W: covers the halo columns of every 16-pixel tile.

@@ -39,50 +39,27 @@ hipError_t launch_bilateral_bwd16(const Plan& P, const BilArgs& a, int pass, hip
 }
 
 namespace bilh {
-// C' (FP32 blocks written by pass 1) -> the split-FP16 volume pass 2 stages,
-// scaled by cprime_scale(max |C'|): level l of stored column s = x + R.
-// Stored columns outside the image and levels past the tile hold zeros.
-__global__ void __launch_bounds__(256) cprime_split_kernel(const float* __restrict__ src,
-                                                           const unsigned int* __restrict__ gmax,
-                                                           uint16_t* __restrict__ dst,
-                                                           int64_t plane, int pitch, int W, int H,
-                                                           int R) {
-  const int l = threadIdx.x & 15;
-  const int s = blockIdx.x * 16 + (threadIdx.x >> 4);
-  const int y = blockIdx.y, blk = blockIdx.z;
-  if (s >= (pitch >> 2)) return;
-  const float S = cprime_scale(*gmax);
-  const int nqx = (W + 3) >> 2;
-  float v[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int c = 4 * s + j - R;
-    v[j] = (c >= 0 && c < W)
-               ? src[(((int64_t)blk * H + y) * nqx + (c >> 2)) * 64 + 4 * l + (c & 3)] * S
-               : 0.0f;
-  }
-  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-  typedef float f2 __attribute__((ext_vector_type(2)));
-  const h2 h01 = __builtin_convertvector((f2){v[0], v[1]}, h2);
-  const h2 h23 = __builtin_convertvector((f2){v[2], v[3]}, h2);
-  const h2 l01 = __builtin_convertvector((f2){v[0] - (float)h01.x, v[1] - (float)h01.y}, h2);
-  const h2 l23 = __builtin_convertvector((f2){v[2] - (float)h23.x, v[3] - (float)h23.y}, h2);
-  const int64_t off = (int64_t)(2 * blk) * plane + (int64_t)y * 16 * pitch + 64 * s + 4 * l;
-  *reinterpret_cast<uint2*>(dst + off) =
-      make_uint2(__builtin_bit_cast(unsigned, h01), __builtin_bit_cast(unsigned, h23));
-  *reinterpret_cast<uint2*>(dst + plane + off) =
-      make_uint2(__builtin_bit_cast(unsigned, l01), __builtin_bit_cast(unsigned, l23));
+// Zeros in the pad columns of every row of the first blocks (both parts):
+// thread t of a row: pad column t / 16 (columns [0, R), then [W + R, pitch)),
+// level t % 16.
+__global__ void __launch_bounds__(256) h2_pad_zero_kernel(uint16_t* __restrict__ h2,
+                                                          int64_t plane, int pitch, int W,
+                                                          int R) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int npad = pitch - W;
+  if (t >= 16 * npad) return;
+  const int ci = t >> 4, l = t & 15;
+  const int c = ci < R ? ci : W + ci;
+  const int y = blockIdx.y, bp = blockIdx.z;   // bp = 2 block + part
+  h2[(int64_t)bp * plane + (int64_t)y * 16 * pitch + 64 * (c >> 2) + 4 * l + (c & 3)] = 0;
 }
-
 }  // namespace bilh
 
-hipError_t launch_cprime_split(const float* cblk, const unsigned int* gmax, uint16_t* h2,
-                               int64_t plane, int pitch, int W, int H, int R, int levels,
-                               hipStream_t s) {
-  if (!cblk || !gmax || !h2 || (pitch & 7) || levels <= 0) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((pitch / 4 + 15) / 16), (unsigned)H, (unsigned)((levels + 15) / 16));
-  hipLaunchKernelGGL(bilh::cprime_split_kernel, grid, dim3(256), 0, s, cblk, gmax, h2, plane,
-                     pitch, W, H, R);
+hipError_t launch_h2_pad_zero(uint16_t* h2, int64_t plane, int pitch, int W, int H, int R,
+                              int nblk, hipStream_t s) {
+  if (!h2 || pitch < W + R || nblk <= 0) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((16 * (pitch - W) + 255) / 256), (unsigned)H, (unsigned)(2 * nblk));
+  hipLaunchKernelGGL(bilh::h2_pad_zero_kernel, grid, dim3(256), 0, s, h2, plane, pitch, W, R);
   return hipGetLastError();
 }
 

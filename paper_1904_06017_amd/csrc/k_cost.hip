@@ -266,7 +266,7 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
                                          const float* __restrict__ isdY,
                                          float* __restrict__ C, int out_w, int64_t out_pitch,
                                          int64_t out_slice, int anchor, int pad, float* sm, int bx,
-                                         int by, int bz) {
+                                         int by, int bz, float* __restrict__ C2 = nullptr) {
   using G = NccGeom<r, DC>;
   constexpr int K = G::K;
   float* As = sm;                         // [ROWS][AW]
@@ -275,7 +275,7 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
   float* Is = Zs + NC_TY * G::ZW;         // [NC_TY][ZW]: 1/sd of the B side
   // split-FP16 output: the tile starts pad columns left of 64 bx, so that
   // lane l writes stored column 64 bx + l and a lane quad is a column quad
-  const int x0 = bx * NC_TX - (QUAD == 2 ? pad : 0);
+  const int x0 = bx * NC_TX - (QUAD >= 2 ? pad : 0);
   const int y0 = by * NC_TY;
   const int d0 = d_first + bz * DC;
   const int SW = W + 2 * r;
@@ -353,7 +353,7 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
           ring[k][s] = h;
         }
         const int y = y0 + yy - 2 * r;        // output row completed by this input row
-        if (yy >= 2 * r && y < H && (QUAD == 2 ? x + pad < out_pitch : x < out_w)) {
+        if (yy >= 2 * r && y < H && (QUAD >= 2 ? x + pad < out_pitch : x < out_w)) {
           const int64_t rowo = (int64_t)y * SW;
           const float zA = anchor ? zY[rowo + cx] : zX[rowo + cx];
           const float iA = (anchor ? isdY[rowo + cx] : isdX[rowo + cx]) * inv_n;
@@ -373,6 +373,8 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
             cq[k] = fmaf(-S * iA, iB, fmaf(zA, zB, 1.0f));
             if (!QUAD)
               C[(int64_t)(d - d_first) * out_slice + (int64_t)y * out_pitch + x] = cq[k];
+            if (QUAD == 3 && x >= 0 && x < W)      // and the planar copy [level][H][W]
+              C2[((int64_t)(d - d_first) * H + y) * W + x] = cq[k];
           }
           if (QUAD == 1) {
             const int q = (d0 + wave * NC_DW - d_first) >> 2;
@@ -380,7 +382,7 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
               reinterpret_cast<float4*>(C)[(int64_t)q * out_slice + (int64_t)y * out_pitch + x] =
                   make_float4(cq[0], cq[1], cq[2], cq[3]);
           }
-          if (QUAD == 2) {
+          if (QUAD >= 2) {
             // this wave's 4 levels of the lane quad's 4 columns, transposed so
             // that lane c of the quad holds level 4 wave + c of all 4 columns;
             // columns outside the image and levels past d_end are zeros
@@ -413,11 +415,11 @@ ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
            const float* __restrict__ zX, const float* __restrict__ isdX,
            const float* __restrict__ zY, const float* __restrict__ isdY,
            float* __restrict__ C, int out_w, int64_t out_pitch,
-           int64_t out_slice, int anchor, int pad) {
+           int64_t out_slice, int anchor, int pad, float* __restrict__ C2) {
   extern __shared__ float sm[];
   ncc_body<r, T, QUAD, DC>(ref, ref_pitch, tarw, W, H, d_first, d_end, zX, isdX, zY, isdY, C,
                        out_w, out_pitch, out_slice, anchor, pad, sm, blockIdx.x, blockIdx.y,
-                       blockIdx.z);
+                       blockIdx.z, C2);
 }
 
 
@@ -491,9 +493,22 @@ hipError_t launch_ncc_rdc(const Plan& P, const T* ref, const float* tar_w, const
                           const float* isdX, const float* zY, const float* isdY, float* C,
                           int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
                           int d_first, int d_end, int quad, int pad,
-                          hipStream_t s) {
+                          hipStream_t s, float* C2) {
   dim3 grid((out_w + NC_TX - 1) / NC_TX, (P.H + NC_TY - 1) / NC_TY,
             (d_end - d_first + DC - 1) / DC);
+  if (quad == 3) {
+    // split-FP16 and planar FP32 outputs in one pass (FP32 images only)
+    if constexpr (std::is_same<T, float>::value) {
+      hipError_t e = ncc_allow_lds<r, T, 3, DC, 0>();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((ncc_kernel<r, T, 3, DC>), grid, dim3(16 * DC),
+                         (NccGeom<r, DC>::lds_bytes), s, ref, P.p.pitch_ref, tar_w, P.W, P.H,
+                         d_first, d_end, zX, isdX, zY, isdY, C, out_w, out_pitch, out_slice,
+                         anchor, pad, C2);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
   hipError_t e = quad == 2 ? ncc_allow_lds<r, T, 2, DC, 0>()
                  : quad ? ncc_allow_lds<r, T, 1, DC, 0>() : ncc_allow_lds<r, T, 0, DC, 0>();
   if (e != hipSuccess) return e;
@@ -501,17 +516,17 @@ hipError_t launch_ncc_rdc(const Plan& P, const T* ref, const float* tar_w, const
     hipLaunchKernelGGL((ncc_kernel<r, T, 2, DC>), grid, dim3(16 * DC),
                        (NccGeom<r, DC>::lds_bytes), s, ref, P.p.pitch_ref, tar_w, P.W, P.H,
                        d_first, d_end, zX, isdX, zY, isdY, C, out_w, out_pitch, out_slice,
-                       anchor, pad);
+                       anchor, pad, (float*)nullptr);
   else if (quad)
     hipLaunchKernelGGL((ncc_kernel<r, T, 1, DC>), grid, dim3(16 * DC),
                        (NccGeom<r, DC>::lds_bytes), s, ref, P.p.pitch_ref, tar_w, P.W, P.H,
                        d_first, d_end, zX, isdX, zY, isdY, C, out_w, out_pitch, out_slice,
-                       anchor, 0);
+                       anchor, 0, (float*)nullptr);
   else
     hipLaunchKernelGGL((ncc_kernel<r, T, 0, DC>), grid, dim3(16 * DC),
                        (NccGeom<r, DC>::lds_bytes), s, ref, P.p.pitch_ref, tar_w, P.W, P.H,
                        d_first, d_end, zX, isdX, zY, isdY, C, out_w, out_pitch, out_slice,
-                       anchor, 0);
+                       anchor, 0, (float*)nullptr);
   return hipGetLastError();
 }
 
@@ -520,7 +535,7 @@ hipError_t launch_ncc_r(const Plan& P, const T* ref, const float* tar_w, const f
                         const float* isdX, const float* zY, const float* isdY, float* C,
                         int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
                         int d_first, int d_end, int quad, int pad,
-                        hipStream_t s) {
+                        hipStream_t s, float* C2) {
   int dc = P.ncc_levels;
   if (dc == 0) {
     // automatic: the smallest block that holds every level, at most 64 (a
@@ -532,13 +547,13 @@ hipError_t launch_ncc_r(const Plan& P, const T* ref, const float* tar_w, const f
   switch (dc) {
     case 32:
       return launch_ncc_rdc<r, T, 32>(P, ref, tar_w, zX, isdX, zY, isdY, C, out_w, out_pitch,
-                                      out_slice, anchor, d_first, d_end, quad, pad, s);
+                                      out_slice, anchor, d_first, d_end, quad, pad, s, C2);
     case 64:
       return launch_ncc_rdc<r, T, 64>(P, ref, tar_w, zX, isdX, zY, isdY, C, out_w, out_pitch,
-                                      out_slice, anchor, d_first, d_end, quad, pad, s);
+                                      out_slice, anchor, d_first, d_end, quad, pad, s, C2);
     default:
       return launch_ncc_rdc<r, T, 16>(P, ref, tar_w, zX, isdX, zY, isdY, C, out_w, out_pitch,
-                                      out_slice, anchor, d_first, d_end, quad, pad, s);
+                                      out_slice, anchor, d_first, d_end, quad, pad, s, C2);
   }
 }
 
@@ -547,11 +562,11 @@ hipError_t launch_ncc_t(const Plan& P, const T* ref, const float* tar_w, const f
                         const float* isdX, const float* zY, const float* isdY, float* C,
                         int out_w, int64_t out_pitch, int64_t out_slice, int anchor,
                         int d_first, int d_end, int quad, int pad,
-                        hipStream_t s) {
+                        hipStream_t s, float* C2) {
 #define NCC_CASE(R_) \
   case R_: return launch_ncc_r<R_, T>(P, ref, tar_w, zX, isdX, zY, isdY, C, out_w, \
                                       out_pitch, out_slice, anchor, d_first, d_end, quad, pad, \
-                                      s);
+                                      s, C2);
   switch (P.r) {
     NCC_CASE(1) NCC_CASE(2) NCC_CASE(3) NCC_CASE(4)
     NCC_CASE(5) NCC_CASE(6) NCC_CASE(7) NCC_CASE(8)
@@ -733,16 +748,17 @@ hipError_t launch_ncc(const Plan& P, const void* ref, const float* tar_w,
                       const float* zX, const float* isdX, const float* zY,
                       const float* isdY, float* C, int out_w, int64_t out_pitch,
                       int64_t out_slice, int anchor, hipStream_t s, int d_first, int d_end,
-                      int quad, int pad) {
+                      int quad, int pad, float* C2) {
   if (d_end < 0) d_end = P.D;
   if (quad == 1 && (d_first & 3)) return hipErrorInvalidValue;
-  if (quad == 2 && (d_first & 15 || pad < 0 || (out_pitch & 7) || out_w < out_pitch))
+  if (quad >= 2 && (d_first & 15 || pad < 0 || (out_pitch & 7) || out_w < out_pitch))
     return hipErrorInvalidValue;
+  if (quad == 3 && (!C2 || P.p.dtype != STEREO_F32)) return hipErrorInvalidValue;
   if (P.p.dtype == STEREO_U8)
     return launch_ncc_t(P, (const uint8_t*)ref, tar_w, zX, isdX, zY, isdY, C, out_w,
-                        out_pitch, out_slice, anchor, d_first, d_end, quad, pad, s);
+                        out_pitch, out_slice, anchor, d_first, d_end, quad, pad, s, C2);
   return launch_ncc_t(P, (const float*)ref, tar_w, zX, isdX, zY, isdY, C, out_w, out_pitch,
-                      out_slice, anchor, d_first, d_end, quad, pad, s);
+                      out_slice, anchor, d_first, d_end, quad, pad, s, C2);
 }
 
 }  // namespace stereo

@@ -103,6 +103,18 @@ guide_finish_kernel(const GT* __restrict__ g, int64_t gpitch, const float* __res
 // then the target-side sums along the diagonals (the second pass re-reads C
 // and dC; one fused pass with the diagonals exchanged through LDS, or read
 // through the caches, measured slower).
+// max |g| over n values into *out (float bits; non-negative floats order as
+// their bits), one atomic per wave; *out is zeroed before the launch.
+__global__ void __launch_bounds__(256) absmax_kernel(const float* __restrict__ g, int64_t n,
+                                                     unsigned int* __restrict__ out) {
+  float m = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    m = fmaxf(m, fabsf(g[i]));
+#pragma unroll
+  for (int k = 1; k < 64; k <<= 1) m = fmaxf(m, __shfl_xor(m, k));
+  if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(out, __float_as_uint(m));
+}
+
 __global__ void __launch_bounds__(kT)
 ncc_coef_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
                 const float* __restrict__ muX, const float* __restrict__ isdX,
@@ -535,8 +547,6 @@ size_t grad_layout(Plan& P, size_t o) {
   for (int i = GR_WP; i <= GR_GTARW; ++i) sz[i] = f4 * HW;
   sz[GR_SUMS] = 3 * f4 * HW;
   for (int i = GR_CT; i <= GR_GCT; ++i) sz[i] = f4 * DT * HW;
-  // the matrix-core backward writes C' in 16-level blocks of column quads
-  sz[GR_GT] = std::max(sz[GR_GT], f4 * ((DT + 15) / 16) * 16 * P.H * (((size_t)P.W + 3) / 4) * 4);
   sz[GR_FA] = f4 * DT * HW;
   sz[GR_BA] = f4 * DT * HV * WVX;
   sz[GR_BS] = 3 * f4 * HV * WVX;
@@ -680,8 +690,20 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
                               const double plane[3], const float* saved, const float* grad_disp,
                               float* grad_ref, float* grad_tar, double* grad_plane, void* ws,
                               size_t ws_bytes, hipStream_t stream) {
+  return stereo_backward_profiled(plan, ref, tar, plane, saved, grad_disp, grad_ref, grad_tar,
+                                  grad_plane, ws, ws_bytes, nullptr, stream);
+}
+
+stereo_status stereo_backward_profiled(stereo_plan_t plan, const float* ref, const float* tar,
+                                       const double plane[3], const float* saved,
+                                       const float* grad_disp, float* grad_ref, float* grad_tar,
+                                       double* grad_plane, void* ws, size_t ws_bytes,
+                                       hipEvent_t* ev, hipStream_t stream) {
   REQ(plan && ref && tar && plane && saved && grad_disp && grad_ref && grad_tar && grad_plane,
       "all arguments must be non-NULL");
+  auto mark = [&](int i) -> hipError_t {
+    return ev ? hipEventRecord(ev[i], stream) : hipSuccess;
+  };
   stereo_status st = check_grad(plan->P, ws, ws_bytes);
   if (st != STEREO_OK) return st;
   REQ(std::isfinite(plane[0]) && std::isfinite(plane[1]) && std::isfinite(plane[2]) &&
@@ -719,6 +741,7 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
   const dim3 flat((unsigned)((HW + 255) / 256));
   const int nb = (int)rows.x * H;
 
+  HIPC(mark(0), "event record");
   // accumulators, cleared by one kernel launch (graph-safe; the fixed-point
   // target accumulator is cleared as two floats per element, all bits zero)
   {
@@ -754,21 +777,28 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
   // (small radii: two weight operands per lane) and the level tiles start on
   // 16-level blocks; elsewhere on the vector ALU
   const bool mc = P.agg_engine == 2 && P.R <= kBwd16MaxR && (D <= DT || DT % 16 == 0);
+  if (mc) {
+    // max |g'| (the scale of C' in pass 1) and zeros in the pad columns of
+    // the C' volume, which the passes never write
+    LAUNCH("max |g'|", absmax_kernel, dim3(240), dim3(256), 0, stream, grad_disp, HW,
+           reinterpret_cast<unsigned int*>(R_(GR_GMAX)));
+    HIPC(launch_h2_pad_zero(at<uint16_t>(ws, P.off_cvol + P.h2_tar_off),
+                            16 * (int64_t)H * P.h2_pitch, P.h2_pitch, W, H, P.R, (DT + 15) / 16,
+                            stream), "pad columns of C'");
+  }
   for (int d0 = 0; d0 < D; d0 += DT) {
     const int nl = std::min(DT, D - d0);
-    // recompute this tile of the cost volume
-    HIPC(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, Ct, W, W, HW, 0, stream, d0,
-                    d0 + nl), "ncc tile");
     // pass 1: aggregated costs E, the softmax adjoint dE, dE / W_p, aP, A1 (and W_p)
     if (mc) {
-      // matrix cores: the tile's costs again, split (reference-anchored
-      // blocks), the two passes over split operands, C' re-split between them
+      // matrix cores: the tile's costs recomputed once into both the split
+      // volume the passes stage and the planar one the NCC adjoint reads;
+      // pass 1 writes C' split for pass 2
       uint16_t* hC = at<uint16_t>(ws, P.off_cvol);
       uint16_t* hG = at<uint16_t>(ws, P.off_cvol + P.h2_tar_off);
       const int64_t hplane = 16 * (int64_t)H * P.h2_pitch;
       HIPC(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, reinterpret_cast<float*>(hC),
-                      P.h2_pitch, P.h2_pitch, hplane, 0, stream, d0, d0 + nl, 2, P.R),
-           "ncc tile (split)");
+                      P.h2_pitch, P.h2_pitch, hplane, 0, stream, d0, d0 + nl, 3, P.R, Ct),
+           "ncc tile (split and planar)");
       BilArgs a{};
       a.h2 = hC; a.h2_plane = hplane; a.h2_pitch = P.h2_pitch;
       a.guide = ref; a.guide_dt = STEREO_F32; a.guide_pitch = P.p.pitch_ref;
@@ -781,16 +811,23 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
       a.aP = aP; a.A1 = A1; a.A2 = A2;
       a.Wp = d0 == 0 ? Wp : nullptr;
       a.d_first = d0;
-      a.gmax = reinterpret_cast<unsigned int*>(R_(GR_GMAX));
+      a.gmax = reinterpret_cast<const unsigned int*>(R_(GR_GMAX));
+      a.h2_out = hG;
       a.plane[0] = plane[0]; a.plane[1] = plane[1]; a.plane[2] = plane[2];
+      if (d0 == 0) HIPC(mark(1), "event record");
       HIPC(launch_bilateral_bwd16(P, a, 1, stream), "aggregation + softmax adjoint");
-      HIPC(launch_cprime_split(Gt, a.gmax, hG, hplane, P.h2_pitch, W, H, P.R, nl, stream),
-           "split of dE / W");
+      if (d0 == 0) HIPC(mark(2), "event record");
+      if (d0 == 0) HIPC(mark(3), "event record");
       a.h2 = hG;
+      a.h2_out = nullptr;
       a.E = gCt;
       a.cpix = Ct;
       HIPC(launch_bilateral_bwd16(P, a, 2, stream), "aggregation adjoint");
+      if (d0 == 0) HIPC(mark(4), "event record");
     } else {
+    // recompute this tile of the cost volume
+    HIPC(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, Ct, W, W, HW, 0, stream, d0,
+                    d0 + nl), "ncc tile");
     BilArgs a{};
     a.C = Ct; a.c_slice = HW; a.c_pitch = W;
     a.guide = ref; a.guide_dt = STEREO_F32; a.guide_pitch = P.p.pitch_ref;
@@ -804,12 +841,16 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
     a.Wp = d0 == 0 ? Wp : nullptr;
     a.d_first = d0;
     a.plane[0] = plane[0]; a.plane[1] = plane[1]; a.plane[2] = plane[2];
+    if (d0 == 0) HIPC(mark(1), "event record");
     HIPC(launch_bilateral(P, a, 5, stream), "aggregation + softmax adjoint");
+    if (d0 == 0) HIPC(mark(2), "event record");
+    if (d0 == 0) HIPC(mark(3), "event record");
     // pass 2: dC(q, d) = sum_p w(q, p) dE(p, d) / W_p (weights are symmetric), A2
     a.C = Gt;
     a.E = gCt;
     a.cpix = Ct;
     HIPC(launch_bilateral(P, a, 6, stream), "aggregation adjoint");
+    if (d0 == 0) HIPC(mark(4), "event record");
     }
     LAUNCH("ncc adjoint coefficients", ncc_coef_kernel, rows, dim3(kT), 0, stream, Ct, gCt,
            muX, m.isdX, muY, m.isdY, W, H, r, d0, nl, 1.0f / (float)n, Fa, Sb, SbmX, SamY);
@@ -842,6 +883,7 @@ stereo_status stereo_backward(stereo_plan_t plan, const float* ref, const float*
          sm_dh, W, H, dp, partA);
   LAUNCH("plane", plane_finish_kernel, dim3(1), dim3(256), 0, stream, partA, nb, 1.0, partB, nb,
          -1.0, grad_plane);
+  HIPC(mark(5), "event record");
   return STEREO_OK;
 }
 
