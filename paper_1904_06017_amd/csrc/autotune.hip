@@ -220,9 +220,9 @@ stereo_status stereo_batch_autotune(stereo_batch_t b, void* ws, size_t ws_bytes,
   // key: architecture + FNV-1a hash of every pair's shape
   uint64_t h = 1469598103934665603ull;
   int32_t n = 0;
-  const char* keys[3] = {"wg_per_cu", "agg_levels_u8", "agg_levels_f32"};
-  int32_t cur[3];
-  for (int k = 0; k < 3; ++k) stereo_batch_get_tuning(b, keys[k], &cur[k]);
+  const char* keys[4] = {"wg_per_cu", "agg_levels_u8", "agg_levels_f32", "tile_band"};
+  int32_t cur[4];
+  for (int k = 0; k < 4; ++k) stereo_batch_get_tuning(b, keys[k], &cur[k]);
   // shapes are hashed through the workspace size and the plan shapes
   size_t wsb = 0;
   stereo_batch_workspace_bytes(b, &wsb);
@@ -246,35 +246,43 @@ stereo_status stereo_batch_autotune(stereo_batch_t b, void* ws, size_t ws_bytes,
   auto cache = load_cache(cache_path);
   auto it = cache.find(key);
   if (it != cache.end() && it->second.count("wg_per_cu")) {
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 4; ++k)
       if (it->second.count(keys[k])) stereo_batch_set_tuning(b, keys[k], (int)it->second[keys[k]]);
     if (best_ms) *best_ms = it->second.count("ms") ? it->second["ms"] : 0.0;
     return STEREO_OK;
   }
-  // the knobs are those of the vector-ALU engine (workgroups per CU, levels
-  // per pass); with the matrix-core engine there is one variant to time
+  // the vector-ALU engine's knobs are its workgroups per CU and levels per
+  // pass; the matrix-core engines' is the band width of their tile list (the
+  // 2-D patch of tiles an XCD works on at a time: L2 reuse of the halos)
   double best = 1e30;
-  int32_t bestv[3] = {cur[0], cur[1], cur[2]};
+  int32_t bestv[4] = {cur[0], cur[1], cur[2], cur[3]};
   stereo_status st = STEREO_OK;
   const std::vector<int> wgs = engine == 0 ? std::vector<int>{1, 2, 3, 4} : std::vector<int>{cur[0]};
   const std::vector<int> lvls = engine == 0 ? std::vector<int>{8, 16} : std::vector<int>{cur[1]};
+  const std::vector<int> bands = engine == 0 ? std::vector<int>{cur[3]}
+                                             : std::vector<int>{2, 4, 8, 16};
   for (int wg : wgs) {
     for (int lv : lvls) {
-      stereo_batch_set_tuning(b, "wg_per_cu", wg);
-      stereo_batch_set_tuning(b, "agg_levels_u8", lv);
-      stereo_batch_set_tuning(b, "agg_levels_f32", lv);
-      double ms = 0.0;
-      st = time_ms(stream, reps, [&]() { return stereo_submit_batch(b, ws, ws_bytes, stream); },
-                   &ms);
+      for (int bd : bands) {
+        stereo_batch_set_tuning(b, "wg_per_cu", wg);
+        stereo_batch_set_tuning(b, "agg_levels_u8", lv);
+        stereo_batch_set_tuning(b, "agg_levels_f32", lv);
+        stereo_batch_set_tuning(b, "tile_band", bd);
+        double ms = 0.0;
+        st = time_ms(stream, reps,
+                     [&]() { return stereo_submit_batch(b, ws, ws_bytes, stream); }, &ms);
+        if (st != STEREO_OK) break;
+        if (ms < best) { best = ms; bestv[0] = wg; bestv[1] = lv; bestv[2] = lv; bestv[3] = bd; }
+      }
       if (st != STEREO_OK) break;
-      if (ms < best) { best = ms; bestv[0] = wg; bestv[1] = lv; bestv[2] = lv; }
     }
     if (st != STEREO_OK) break;
   }
-  for (int k = 0; k < 3; ++k) stereo_batch_set_tuning(b, keys[k], bestv[k]);
+  for (int k = 0; k < 4; ++k) stereo_batch_set_tuning(b, keys[k], bestv[k]);
   if (st != STEREO_OK) return st;
   cache[key] = Entry{{"wg_per_cu", (double)bestv[0]}, {"agg_levels_u8", (double)bestv[1]},
-                     {"agg_levels_f32", (double)bestv[2]}, {"ms", best}};
+                     {"agg_levels_f32", (double)bestv[2]}, {"tile_band", (double)bestv[3]},
+                     {"ms", best}};
   save_cache(cache_path, cache);
   if (best_ms) *best_ms = best;
   return STEREO_OK;

@@ -63,6 +63,7 @@ struct stereo_batch_s {
   std::vector<char> host_desc;         // descriptors bound to the last workspace
   void* bound_ws = nullptr;
   int wg_per_cu = 2;
+  int tile_band = 4;                   // tile columns per band of the matrix-core tile list
   int levels_u8 = 8, levels_f32 = 8;
   int engine = 2;                      // aggregation engine: 2 / 1 matrix cores with split-FP16
                                        // / FP32 operands, 0 vector ALU
@@ -88,8 +89,6 @@ T* at(void* ws, size_t off) {
 // covers the extended columns (anchor 0 only), the split-FP16 volumes the
 // stored rows of both anchors (the target-anchored one when the pair has an
 // LR check).
-constexpr int kBandTiles = 4;   // tile columns per band of the matrix-core tile order
-
 void ncc_blocks(stereo_batch_s& b) {
   for (JobList& L : b.lists) {
     if (L.kind != JK_NCC) continue;
@@ -136,11 +135,12 @@ void build_layout(stereo_batch_s& b) {
       const int gi = find_group(P.R, g);
       for (int y = 0; y < P.H; y += kBilTileH)
         for (int x = 0; x < P.W; x += kBilTileW) per[gi].push_back({P.D, i, vol, x, y});
-      // matrix-core tiles in bands of kBandTiles tile columns walked row by
+      // matrix-core tiles in bands of tile_band tile columns walked row by
       // row: a run of the list is a 2-D patch of the image (shared halos)
-      for (int xb = 0; xb < P.W; xb += kBandTiles * kMfmaTileW)
+      const int bandw = b.tile_band * kMfmaTileW;
+      for (int xb = 0; xb < P.W; xb += bandw)
         for (int y = 0; y < P.H; y += kMfmaTileH)
-          for (int x = xb; x < std::min(P.W, xb + kBandTiles * kMfmaTileW); x += kMfmaTileW)
+          for (int x = xb; x < std::min(P.W, xb + bandw); x += kMfmaTileW)
             per_m[gi].push_back({P.D, i, vol, x, y});
     }
   }
@@ -449,6 +449,14 @@ stereo_status stereo_batch_set_tuning(stereo_batch_t b, const char* key, int32_t
     BREQ(value == 8 || value == 16, "%s must be 8 or 16", key);
     (k == "agg_levels_u8" ? b->levels_u8 : b->levels_f32) = value;
     for (Group& G : b->groups) G.levels = G.gdt == STEREO_U8 ? b->levels_u8 : b->levels_f32;
+  } else if (k == "tile_band") {
+    BREQ(value == 1 || value == 2 || value == 4 || value == 8 || value == 16 || value == 32,
+         "tile_band must be 1, 2, 4, 8, 16 or 32");
+    if (value != b->tile_band) {
+      b->tile_band = value;
+      build_layout(*b);                 // the same sizes and offsets, another tile order
+      b->bound_ws = nullptr;            // tables are uploaded again
+    }
   } else if (k == "agg_engine") {
     BREQ(value >= 0 && value <= 2,
          "agg_engine must be 0 (vector ALU), 1 (matrix cores, FP32 operands) or 2 (matrix "
@@ -466,6 +474,7 @@ stereo_status stereo_batch_get_tuning(stereo_batch_t b, const char* key, int32_t
   BREQ(b && key && value, "batch, key and value must be non-NULL");
   const std::string k(key);
   if (k == "wg_per_cu") *value = b->wg_per_cu;
+  else if (k == "tile_band") *value = b->tile_band;
   else if (k == "agg_levels_u8") *value = b->levels_u8;
   else if (k == "agg_levels_f32") *value = b->levels_f32;
   else if (k == "agg_engine") *value = b->engine;

@@ -117,14 +117,16 @@ def test_batch_tuning_does_not_change_results(small_batch):
     items = _make(small_batch)
     b = api.Batch(items)
     ref = [{k: _host(v) for k, v in o.items()} for o in b.submit()]
-    for wg, lv in ((1, 16), (4, 8)):
+    for wg, lv, band in ((1, 16, 1), (4, 8, 32), (2, 8, 2)):
         b.set_tuning("wg_per_cu", wg)
         b.set_tuning("agg_levels_u8", lv)
         b.set_tuning("agg_levels_f32", lv)
+        b.set_tuning("tile_band", band)      # the matrix-core engine's tile order
+        assert b.get_tuning("tile_band") == band
         got = [{k: _host(v) for k, v in o.items()} for o in b.submit()]
         for e, g in zip(ref, got):
             for k in e:
-                assert np.array_equal(e[k], g[k], equal_nan=True), (wg, lv, k)
+                assert np.array_equal(e[k], g[k], equal_nan=True), (wg, lv, band, k)
 
 
 def test_batch_pairs_match_the_oracle(small_batch):
@@ -169,7 +171,12 @@ def test_batch_autotune(small_batch, tmp_path):
     cache = str(tmp_path / "btune.json")
     ms = b.autotune(cache, reps=1)
     assert ms > 0
-    assert "batch" in next(iter(json.load(open(cache))))
+    entries = json.load(open(cache))
+    key = next(iter(entries))
+    assert "batch" in key
+    # the default engine's knob was swept and the choice applied
+    assert int(entries[key]["tile_band"]) in (2, 4, 8, 16)
+    assert b.get_tuning("tile_band") == int(entries[key]["tile_band"])
     got = [{k: _host(v) for k, v in o.items()} for o in b.submit()]
     for e, g in zip(ref, got):
         for k in e:
