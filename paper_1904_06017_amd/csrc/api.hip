@@ -369,18 +369,16 @@ stereo_status match_impl(stereo_plan_t plan, const void* ref, const void* tar,
   const bool lr = P.p.lr_check != 0;
   BilArgs a{};
   if (P.agg_engine == 2) {
-    // Split-FP16 volumes for the FP16-operand matrix cores, one NCC launch
-    // per anchor: the reference-anchored volume and, for the LR check, the
+    // Split-FP16 volumes for the FP16-operand matrix cores from one NCC
+    // pass: the reference-anchored volume and, for the LR check, the
     // target-anchored one (each stored by the column it is aggregated at).
     uint16_t* vR = at<uint16_t>(ws, P.off_cvol);
     uint16_t* vT = at<uint16_t>(ws, P.off_cvol + P.h2_tar_off);
     const int64_t plane = 16 * (int64_t)P.H * P.h2_pitch;
     STEREO_HIP(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY, reinterpret_cast<float*>(vR),
-                          P.h2_pitch, P.h2_pitch, plane, 0, stream, 0, -1, 2, P.R), "ncc");
-    if (lr)
-      STEREO_HIP(launch_ncc(P, ref, tarw, m.zX, m.isdX, m.zY, m.isdY,
-                            reinterpret_cast<float*>(vT), P.h2_pitch, P.h2_pitch, plane, 1,
-                            stream, 0, -1, 2, P.R), "ncc (target-anchored)");
+                          ncc_both_extent(P.h2_pitch, 0, P.D), P.h2_pitch, plane, 0, stream, 0,
+                          -1, 4, P.R, lr ? reinterpret_cast<float*>(vT) : nullptr),
+               "ncc (both anchors)");
     a.h2 = vR;
     a.h2_plane = plane;
     a.h2_pitch = P.h2_pitch;

@@ -86,9 +86,14 @@ T* at(void* ws, size_t off) {
 }
 
 // Block prefix of the NCC job lists for the batch's engine: the quad volume
-// covers the extended columns (anchor 0 only), the split-FP16 volumes the
-// stored rows of both anchors (the target-anchored one when the pair has an
-// LR check).
+// covers the extended columns (anchor 0 only); the split-FP16 engine writes
+// both anchors' volumes (the target-anchored one when the pair has an LR
+// check) from one job over the stored row plus the levels.
+// Levels per NCC workgroup of a job list: the both-anchors form of the
+// split-FP16 engine runs at most 32 (its register count fits two 16-wave
+// workgroups per CU only below that).
+int ncc_dc(const JobList& L, int engine) { return engine == 2 ? std::min(L.dc, 32) : L.dc; }
+
 void ncc_blocks(stereo_batch_s& b) {
   for (JobList& L : b.lists) {
     if (L.kind != JK_NCC) continue;
@@ -96,10 +101,11 @@ void ncc_blocks(stereo_batch_s& b) {
       const Plan& P = b.plans[L.pair[k]];
       int blocks = 0;
       if (b.engine == 2) {
-        if (L.which[k] == 0 || P.p.lr_check)
-          blocks = ncc_job_blocks(P, P.h2_pitch, 0, P.D, L.dc);
+        if (L.which[k] == 0)
+          blocks = ncc_job_blocks(P, ncc_both_extent(P.h2_pitch, 0, P.D), 0, P.D,
+                                  ncc_dc(L, b.engine), 4);
       } else if (L.which[k] == 0) {
-        blocks = ncc_job_blocks(P, P.W + P.D - 1, 0, P.D, L.dc);
+        blocks = ncc_job_blocks(P, P.W + P.D - 1, 0, P.D, L.dc, 1);
       }
       L.first[k + 1] = L.first[k] + blocks;
     }
@@ -193,9 +199,9 @@ void build_layout(stereo_batch_s& b) {
     Lt.r = std::max(Lt.r, P.r);
   }
   // NCC: the level block of the list's smallest pair (the smallest block that
-  // holds its levels, at most 64); two jobs per pair (which = the anchor:
-  // the target-anchored one runs only for the split-FP16 engine), their
-  // blocks set per engine by ncc_blocks
+  // holds its levels, at most 64); two job slots per pair (which = 0: the
+  // job, covering both anchors with the split-FP16 engine; which = 1 has no
+  // blocks), their blocks set per engine by ncc_blocks
   for (int i = 0; i < n; ++i) {
     const Plan& P = b.plans[i];
     JobList& L = list_of(JK_NCC, P.p.dtype, P.r);
@@ -291,16 +297,17 @@ stereo_status bind(stereo_batch_s& b, void* ws, size_t bytes, hipStream_t s) {
       } else if (L.kind == JK_NCC) {
         NccJob J;
         if (b.engine == 2) {
-          // anchor = which: the reference- or the target-anchored volume
-          const int anchor = L.which[k];
+          // both anchored split volumes from one job (which = 0; the second
+          // job of the pair has no blocks)
           J = ncc_job(P, b.items[i].ref, tarw, st, st + sn, st + 2 * sn, st + 3 * sn,
-                      at<float>(pws, P.off_cvol + (anchor ? P.h2_tar_off : 0)), P.h2_pitch,
-                      P.h2_pitch, 16 * (int64_t)P.H * P.h2_pitch, anchor, 0, P.D);
+                      at<float>(pws, P.off_cvol), ncc_both_extent(P.h2_pitch, 0, P.D),
+                      P.h2_pitch, 16 * (int64_t)P.H * P.h2_pitch, 0, 0, P.D, 4,
+                      P.p.lr_check ? at<float>(pws, P.off_cvol + P.h2_tar_off) : nullptr);
           J.pad = P.R;
         } else {
           J = ncc_job(P, b.items[i].ref, tarw, st, st + sn, st + 2 * sn, st + 3 * sn,
                       at<float>(pws, P.off_cvol), P.W + P.D - 1, P.cw, (int64_t)P.H * P.cw, 0,
-                      0, P.D);
+                      0, P.D, 1, nullptr);
         }
         memcpy(dst, &J, sizeof(J));
       } else {
@@ -345,7 +352,7 @@ stereo_status enqueue(stereo_batch_s& b, hipStream_t s, hipEvent_t* ev = nullptr
                                s), "batch statistics");
         break;
       case JK_NCC:
-        BHIP(launch_ncc_jobs(L.r, L.dt, b.engine == 2 ? 2 : 1, L.dc,
+        BHIP(launch_ncc_jobs(L.r, L.dt, b.engine == 2 ? 4 : 1, ncc_dc(L, b.engine),
                              static_cast<const NccJob*>(jobs), first, nj, blocks, s),
              "batch ncc");
         break;

@@ -99,7 +99,9 @@ hipError_t launch_block_stats(const Plan& P, const void* img, stereo_dtype dt,
 // columns (a multiple of 8), out_slice = 16 H out_pitch, out_w >= out_pitch,
 // pad = column shift (the window radius R), d_first a multiple of 16.
 // quad = 3 (FP32 images): both the split-FP16 volume in C (as quad 2) and
-// the planar FP32 volume [levels][H][W] in C2, from one pass.
+// the planar FP32 volume [levels][H][W] in C2, from one pass.  quad = 4:
+// the reference-anchored split volume in C and the target-anchored one in
+// C2 (nullable) from one pass; out_w = ncc_both_extent(out_pitch, ...).
 hipError_t launch_ncc(const Plan& P, const void* ref, const float* tar_w,
                       const float* zX, const float* isdX, const float* zY,
                       const float* isdY, float* C, int out_w, int64_t out_pitch,
@@ -228,7 +230,8 @@ struct NccJob {             // grid: gx = ceil(out_w / 64) x gy = ceil(H / 32) x
   const float *zX, *isdX, *zY, *isdY;
   float* C; int64_t out_pitch, out_slice;
   int W, H, d_first, d_end, out_w, anchor, gx, gy;
-  int pad;                    // split-FP16 output (quad = 2): column shift
+  int pad;                    // split-FP16 output (quad = 2, 4): column shift
+  float* C2;                  // quad = 4: the target-anchored volume (nullable)
 };
 struct LrJob {              // grid: gx = ceil(W / 256) x H rows
   const int16_t* dR; const int16_t* dT; const float* dsub; uint8_t* valid; float* disp;
@@ -240,13 +243,17 @@ struct LrJob {              // grid: gx = ceil(W / 256) x H rows
 };
 int warp_job_blocks(const Plan& P);
 int stats_job_blocks(int W, int H, int r);
-int ncc_job_blocks(const Plan& P, int out_w, int d_first, int d_end, int dc);
+int ncc_job_blocks(const Plan& P, int out_w, int d_first, int d_end, int dc, int quad);
+// Columns a quad = 4 launch covers (its out_w): the stored row plus the
+// levels rounded up to 16, so that every target-anchored column is reached.
+int ncc_both_extent(int out_pitch, int d_first, int d_end);
 int lr_job_blocks(const Plan& P);
 WarpJob warp_job(const Plan& P, const void* tar, float* tar_w);
 StatsJob stats_job(const Plan& P, const void* img, int64_t pitch, float* z, float* isd);
 NccJob ncc_job(const Plan& P, const void* ref, const float* tar_w, const float* zX,
                const float* isdX, const float* zY, const float* isdY, float* C, int out_w,
-               int64_t out_pitch, int64_t out_slice, int anchor, int d_first, int d_end);
+               int64_t out_pitch, int64_t out_slice, int anchor, int d_first, int d_end,
+               int quad, float* C2);
 LrJob lr_job(const Plan& P, const int16_t* dR, const int16_t* dT, const float* dsub,
              uint8_t* valid, float* disp);
 // jobs / first are device arrays; dt is the element type of the job images

@@ -220,7 +220,17 @@ struct NccGeom {
 // quad and, after a transpose within the quad, each lane writes 4 columns of
 // one level as 8 bytes; the grid's columns cover the stored row
 // (out_w >= out_pitch), columns outside [0, W) and the last block's levels at
-// or past d_end are written as zeros.
+// or past d_end are written as zeros.  QUAD = 4 writes both anchors' split
+// volumes from one pass (the target-anchored one to C2 when non-NULL): the
+// cost of reference column x at level d is also the target-anchored cost of
+// column m = x - d, the same two blocks and the same products.  Tiles step
+// by NC_TX4 = 60 columns; lane x + k holds level d + k of target column m,
+// so three lane shifts (level k from k lanes to the right) line a quad of
+// lanes up with a stored column quad of that volume, after which the same
+// transpose gives 8-byte stores.  The last quad of lanes only feeds the
+// shifts.  The grid covers x < out_w = stored row + the 16-rounded levels,
+// so that every target column, pads included, is written at every level.
+constexpr int NC_TX4 = 60;
 // 4x4 transpose within each quad of lanes (lane c of a quad holds v[0..3];
 // afterwards v[k] holds what lane k held in element c): two butterfly stages
 // of DPP quad permutations, swapping the off-diagonal 2x2 blocks.
@@ -275,7 +285,7 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
   float* Is = Zs + NC_TY * G::ZW;         // [NC_TY][ZW]: 1/sd of the B side
   // split-FP16 output: the tile starts pad columns left of 64 bx, so that
   // lane l writes stored column 64 bx + l and a lane quad is a column quad
-  const int x0 = bx * NC_TX - (QUAD >= 2 ? pad : 0);
+  const int x0 = QUAD == 4 ? bx * NC_TX4 - pad : bx * NC_TX - (QUAD >= 2 ? pad : 0);
   const int y0 = by * NC_TY;
   const int d0 = d_first + bz * DC;
   const int SW = W + 2 * r;
@@ -353,7 +363,8 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
           ring[k][s] = h;
         }
         const int y = y0 + yy - 2 * r;        // output row completed by this input row
-        if (yy >= 2 * r && y < H && (QUAD >= 2 ? x + pad < out_pitch : x < out_w)) {
+        if (yy >= 2 * r && y < H &&
+            (QUAD == 4 ? true : QUAD >= 2 ? x + pad < out_pitch : x < out_w)) {
           const int64_t rowo = (int64_t)y * SW;
           const float zA = anchor ? zY[rowo + cx] : zX[rowo + cx];
           const float iA = (anchor ? isdY[rowo + cx] : isdX[rowo + cx]) * inv_n;
@@ -389,17 +400,45 @@ __device__ __forceinline__ void ncc_body(const T* __restrict__ ref, int64_t ref_
             float v[NC_DW];
 #pragma unroll
             for (int k = 0; k < NC_DW; ++k) v[k] = (x >= 0 && x < W) ? cq[k] : 0.0f;
+            // the target-anchored copy (QUAD 4): level k from lane + k, all
+            // for target column m = x - (first level of the wave)
+            const int db = d0 + wave * NC_DW;
+            float u[NC_DW];
+            if (QUAD == 4 && C2) {
+#pragma unroll
+              for (int k = 0; k < NC_DW; ++k) u[k] = k ? __shfl_down(cq[k], k, 64) : cq[k];
+              const int m = x - db;
+#pragma unroll
+              for (int k = 0; k < NC_DW; ++k) u[k] = (m >= 0 && m < W) ? u[k] : 0.0f;
+            }
             quad_transpose4(v, lane);
-            const int dl = d0 + wave * NC_DW + (lane & 3);
-            if (dl < ((d_end + 15) & ~15)) {
-              uint2 hi, lo;
-              split4_f16(v, hi, lo);
-              // stored column quad 16 bx + lane / 4 of row y, level dl
-              const int64_t off = (int64_t)(2 * ((dl - d_first) >> 4)) * out_slice +
-                                  (int64_t)y * 16 * out_pitch + 64 * (16 * bx + (lane >> 2)) +
-                                  4 * (dl & 15);
-              *reinterpret_cast<uint2*>(reinterpret_cast<_Float16*>(C) + off) = hi;
-              *reinterpret_cast<uint2*>(reinterpret_cast<_Float16*>(C) + out_slice + off) = lo;
+            const int dl = db + (lane & 3);
+            const bool full = QUAD != 4 || lane < NC_TX4;
+            if (dl < ((d_end + 15) & ~15) && full) {
+              // stored column quad of row y, level dl
+              const int sq = (QUAD == 4 ? NC_TX4 / 4 : 16) * bx + (lane >> 2);
+              if (QUAD != 4 || 4 * sq < out_pitch) {
+                uint2 hi, lo;
+                split4_f16(v, hi, lo);
+                const int64_t off = (int64_t)(2 * ((dl - d_first) >> 4)) * out_slice +
+                                    (int64_t)y * 16 * out_pitch + 64 * sq + 4 * (dl & 15);
+                *reinterpret_cast<uint2*>(reinterpret_cast<_Float16*>(C) + off) = hi;
+                *reinterpret_cast<uint2*>(reinterpret_cast<_Float16*>(C) + out_slice + off) = lo;
+              }
+            }
+            if (QUAD == 4 && C2) {
+              quad_transpose4(u, lane);
+              // target-anchored stored column quad: x0 + pad = 60 bx and the
+              // wave's first level are multiples of 4
+              const int s1 = NC_TX4 * bx + 4 * (lane >> 2) - db;
+              if (dl < ((d_end + 15) & ~15) && full && s1 >= 0 && s1 + 4 <= out_pitch) {
+                uint2 hi, lo;
+                split4_f16(u, hi, lo);
+                const int64_t off = (int64_t)(2 * ((dl - d_first) >> 4)) * out_slice +
+                                    (int64_t)y * 16 * out_pitch + 16 * s1 + 4 * (dl & 15);
+                *reinterpret_cast<uint2*>(reinterpret_cast<_Float16*>(C2) + off) = hi;
+                *reinterpret_cast<uint2*>(reinterpret_cast<_Float16*>(C2) + out_slice + off) = lo;
+              }
             }
           }
         }
@@ -469,7 +508,7 @@ ncc_jobs_kernel(const NccJob* __restrict__ jobs, const int* __restrict__ first, 
   const int bz = l / gxy, rem = l - bz * gxy;
   ncc_body<r, T, QUAD, DC>(static_cast<const T*>(J.ref), J.ref_pitch, J.tarw, J.W, J.H, J.d_first,
                        J.d_end, J.zX, J.isdX, J.zY, J.isdY, J.C, J.out_w, J.out_pitch,
-                       J.out_slice, J.anchor, J.pad, sm, rem % J.gx, rem / J.gx, bz);
+                       J.out_slice, J.anchor, J.pad, sm, rem % J.gx, rem / J.gx, bz, J.C2);
 }
 
 // Dynamic LDS above the 64 KB default (large radii at 64 levels), set once
@@ -496,6 +535,17 @@ hipError_t launch_ncc_rdc(const Plan& P, const T* ref, const float* tar_w, const
                           hipStream_t s, float* C2) {
   dim3 grid((out_w + NC_TX - 1) / NC_TX, (P.H + NC_TY - 1) / NC_TY,
             (d_end - d_first + DC - 1) / DC);
+  if (quad == 4) {
+    // both anchors' split volumes (C, and C2 when non-NULL)
+    grid.x = (out_w + NC_TX4 - 1) / NC_TX4;
+    hipError_t e = ncc_allow_lds<r, T, 4, DC, 0>();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((ncc_kernel<r, T, 4, DC>), grid, dim3(16 * DC),
+                       (NccGeom<r, DC>::lds_bytes), s, ref, P.p.pitch_ref, tar_w, P.W, P.H,
+                       d_first, d_end, zX, isdX, zY, isdY, C, out_w, out_pitch, out_slice,
+                       0, pad, C2);
+    return hipGetLastError();
+  }
   if (quad == 3) {
     // split-FP16 and planar FP32 outputs in one pass (FP32 images only)
     if constexpr (std::is_same<T, float>::value) {
@@ -543,6 +593,10 @@ hipError_t launch_ncc_r(const Plan& P, const T* ref, const float* tar_w, const f
     // levels, which pays even when its last levels are idle)
     const int nl = d_end - d_first;
     dc = nl > 32 ? 64 : nl > 16 ? 32 : 16;
+    // the both-anchors form needs more registers (70 at r = 3): a 64-level
+    // workgroup (16 waves) then fits once per CU, two 32-level ones twice
+    // (1280x720, D = 64: 0.167 against 0.181 ms)
+    if (quad == 4 && dc == 64) dc = 32;
   }
   switch (dc) {
     case 32:
@@ -581,9 +635,13 @@ int warp_job_blocks(const Plan& P) { return ((P.W + 255) / 256) * P.H; }
 int stats_job_blocks(int W, int H, int r) {
   return ((W + 2 * r + ST_TX - 1) / ST_TX) * ((H + ST_TY - 1) / ST_TY);
 }
-int ncc_job_blocks(const Plan& P, int out_w, int d_first, int d_end, int dc) {
-  return ((out_w + NC_TX - 1) / NC_TX) * ((P.H + NC_TY - 1) / NC_TY) *
+int ncc_job_blocks(const Plan& P, int out_w, int d_first, int d_end, int dc, int quad) {
+  const int tx = quad == 4 ? NC_TX4 : NC_TX;
+  return ((out_w + tx - 1) / tx) * ((P.H + NC_TY - 1) / NC_TY) *
          ((d_end - d_first + dc - 1) / dc);
+}
+int ncc_both_extent(int out_pitch, int d_first, int d_end) {
+  return out_pitch + (((d_end - d_first) + 15) & ~15);
 }
 
 WarpJob warp_job(const Plan& P, const void* tar, float* tar_w) {
@@ -607,14 +665,17 @@ StatsJob stats_job(const Plan& P, const void* img, int64_t pitch, float* z, floa
 
 NccJob ncc_job(const Plan& P, const void* ref, const float* tar_w, const float* zX,
                const float* isdX, const float* zY, const float* isdY, float* C, int out_w,
-               int64_t out_pitch, int64_t out_slice, int anchor, int d_first, int d_end) {
+               int64_t out_pitch, int64_t out_slice, int anchor, int d_first, int d_end,
+               int quad, float* C2) {
   NccJob J{};
+  J.C2 = C2;
   J.ref = ref; J.ref_pitch = P.p.pitch_ref; J.tarw = tar_w;
   J.zX = zX; J.isdX = isdX; J.zY = zY; J.isdY = isdY;
   J.C = C; J.out_pitch = out_pitch; J.out_slice = out_slice;
   J.W = P.W; J.H = P.H; J.d_first = d_first; J.d_end = d_end < 0 ? P.D : d_end;
   J.out_w = out_w; J.anchor = anchor;
-  J.gx = (out_w + NC_TX - 1) / NC_TX; J.gy = (P.H + NC_TY - 1) / NC_TY;
+  const int tx = quad == 4 ? NC_TX4 : NC_TX;
+  J.gx = (out_w + tx - 1) / tx; J.gy = (P.H + NC_TY - 1) / NC_TY;
   return J;
 }
 
@@ -644,10 +705,14 @@ namespace {
 template <int r, typename T, int DC>
 hipError_t ncc_jobs_rdc(int quad, const NccJob* jobs, const int* first, int n, int blocks,
                         hipStream_t s) {
-  hipError_t e = quad == 2 ? ncc_allow_lds<r, T, 2, DC, 1>()
+  hipError_t e = quad == 4 ? ncc_allow_lds<r, T, 4, DC, 1>()
+                 : quad == 2 ? ncc_allow_lds<r, T, 2, DC, 1>()
                  : quad ? ncc_allow_lds<r, T, 1, DC, 1>() : ncc_allow_lds<r, T, 0, DC, 1>();
   if (e != hipSuccess) return e;
-  if (quad == 2)
+  if (quad == 4)
+    hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 4, DC>), dim3(blocks), dim3(16 * DC),
+                       (NccGeom<r, DC>::lds_bytes), s, jobs, first, n);
+  else if (quad == 2)
     hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 2, DC>), dim3(blocks), dim3(16 * DC),
                        (NccGeom<r, DC>::lds_bytes), s, jobs, first, n);
   else if (quad)
@@ -752,6 +817,8 @@ hipError_t launch_ncc(const Plan& P, const void* ref, const float* tar_w,
   if (d_end < 0) d_end = P.D;
   if (quad == 1 && (d_first & 3)) return hipErrorInvalidValue;
   if (quad >= 2 && (d_first & 15 || pad < 0 || (out_pitch & 7) || out_w < out_pitch))
+    return hipErrorInvalidValue;
+  if (quad == 4 && out_w < ncc_both_extent((int)out_pitch, d_first, d_end))
     return hipErrorInvalidValue;
   if (quad == 3 && (!C2 || P.p.dtype != STEREO_F32)) return hipErrorInvalidValue;
   if (P.p.dtype == STEREO_U8)
