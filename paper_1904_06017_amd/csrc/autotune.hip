@@ -220,9 +220,11 @@ stereo_status stereo_batch_autotune(stereo_batch_t b, void* ws, size_t ws_bytes,
   // key: architecture + FNV-1a hash of every pair's shape
   uint64_t h = 1469598103934665603ull;
   int32_t n = 0;
-  const char* keys[4] = {"wg_per_cu", "agg_levels_u8", "agg_levels_f32", "tile_band"};
-  int32_t cur[4];
-  for (int k = 0; k < 4; ++k) stereo_batch_get_tuning(b, keys[k], &cur[k]);
+  constexpr int NK = 5;
+  const char* keys[NK] = {"wg_per_cu", "agg_levels_u8", "agg_levels_f32", "tile_band",
+                          "ncc_levels"};
+  int32_t cur[NK];
+  for (int k = 0; k < NK; ++k) stereo_batch_get_tuning(b, keys[k], &cur[k]);
   // shapes are hashed through the workspace size and the plan shapes
   size_t wsb = 0;
   stereo_batch_workspace_bytes(b, &wsb);
@@ -246,43 +248,49 @@ stereo_status stereo_batch_autotune(stereo_batch_t b, void* ws, size_t ws_bytes,
   auto cache = load_cache(cache_path);
   auto it = cache.find(key);
   if (it != cache.end() && it->second.count("wg_per_cu")) {
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < NK; ++k)
       if (it->second.count(keys[k])) stereo_batch_set_tuning(b, keys[k], (int)it->second[keys[k]]);
     if (best_ms) *best_ms = it->second.count("ms") ? it->second["ms"] : 0.0;
     return STEREO_OK;
   }
   // the vector-ALU engine's knobs are its workgroups per CU and levels per
-  // pass; the matrix-core engines' is the band width of their tile list (the
-  // 2-D patch of tiles an XCD works on at a time: L2 reuse of the halos)
+  // pass; the matrix-core engines' are the band width of their tile list (the
+  // 2-D patch of tiles an XCD works on at a time: L2 reuse of the halos) and
+  // the NCC level block of the batch's job lists
   double best = 1e30;
-  int32_t bestv[4] = {cur[0], cur[1], cur[2], cur[3]};
+  int32_t bestv[NK] = {cur[0], cur[1], cur[2], cur[3], cur[4]};
   stereo_status st = STEREO_OK;
   const std::vector<int> wgs = engine == 0 ? std::vector<int>{1, 2, 3, 4} : std::vector<int>{cur[0]};
   const std::vector<int> lvls = engine == 0 ? std::vector<int>{8, 16} : std::vector<int>{cur[1]};
   const std::vector<int> bands = engine == 0 ? std::vector<int>{cur[3]}
                                              : std::vector<int>{2, 4, 8, 16};
-  for (int wg : wgs) {
-    for (int lv : lvls) {
-      for (int bd : bands) {
-        stereo_batch_set_tuning(b, "wg_per_cu", wg);
-        stereo_batch_set_tuning(b, "agg_levels_u8", lv);
-        stereo_batch_set_tuning(b, "agg_levels_f32", lv);
-        stereo_batch_set_tuning(b, "tile_band", bd);
-        double ms = 0.0;
-        st = time_ms(stream, reps,
-                     [&]() { return stereo_submit_batch(b, ws, ws_bytes, stream); }, &ms);
-        if (st != STEREO_OK) break;
-        if (ms < best) { best = ms; bestv[0] = wg; bestv[1] = lv; bestv[2] = lv; bestv[3] = bd; }
-      }
-      if (st != STEREO_OK) break;
-    }
+  const std::vector<int> nccs = engine == 0 ? std::vector<int>{cur[4]}
+                                            : std::vector<int>{16, 32, 64};
+  for (size_t v = 0; v < wgs.size() * lvls.size() * bands.size() * nccs.size(); ++v) {
+    size_t q = v;
+    const int nv = nccs[q % nccs.size()]; q /= nccs.size();
+    const int bd = bands[q % bands.size()]; q /= bands.size();
+    const int lv = lvls[q % lvls.size()]; q /= lvls.size();
+    const int wg = wgs[q];
+    stereo_batch_set_tuning(b, "wg_per_cu", wg);
+    stereo_batch_set_tuning(b, "agg_levels_u8", lv);
+    stereo_batch_set_tuning(b, "agg_levels_f32", lv);
+    stereo_batch_set_tuning(b, "tile_band", bd);
+    stereo_batch_set_tuning(b, "ncc_levels", nv);
+    double ms = 0.0;
+    st = time_ms(stream, reps,
+                 [&]() { return stereo_submit_batch(b, ws, ws_bytes, stream); }, &ms);
     if (st != STEREO_OK) break;
+    if (ms < best) {
+      best = ms;
+      bestv[0] = wg; bestv[1] = lv; bestv[2] = lv; bestv[3] = bd; bestv[4] = nv;
+    }
   }
-  for (int k = 0; k < 4; ++k) stereo_batch_set_tuning(b, keys[k], bestv[k]);
+  for (int k = 0; k < NK; ++k) stereo_batch_set_tuning(b, keys[k], bestv[k]);
   if (st != STEREO_OK) return st;
   cache[key] = Entry{{"wg_per_cu", (double)bestv[0]}, {"agg_levels_u8", (double)bestv[1]},
                      {"agg_levels_f32", (double)bestv[2]}, {"tile_band", (double)bestv[3]},
-                     {"ms", best}};
+                     {"ncc_levels", (double)bestv[4]}, {"ms", best}};
   save_cache(cache_path, cache);
   if (best_ms) *best_ms = best;
   return STEREO_OK;

@@ -64,6 +64,7 @@ struct stereo_batch_s {
   void* bound_ws = nullptr;
   int wg_per_cu = 2;
   int tile_band = 4;                   // tile columns per band of the matrix-core tile list
+  int ncc_levels = 0;                  // NCC levels per workgroup (0: automatic)
   int levels_u8 = 8, levels_f32 = 8;
   int engine = 2;                      // aggregation engine: 2 / 1 matrix cores with split-FP16
                                        // / FP32 operands, 0 vector ALU
@@ -92,7 +93,10 @@ T* at(void* ws, size_t off) {
 // Levels per NCC workgroup of a job list: the both-anchors form of the
 // split-FP16 engine runs at most 32 (its register count fits two 16-wave
 // workgroups per CU only below that).
-int ncc_dc(const JobList& L, int engine) { return engine == 2 ? std::min(L.dc, 32) : L.dc; }
+int ncc_dc(const stereo_batch_s& b, const JobList& L) {
+  if (b.ncc_levels) return b.ncc_levels;
+  return b.engine == 2 ? std::min(L.dc, 32) : L.dc;
+}
 
 void ncc_blocks(stereo_batch_s& b) {
   for (JobList& L : b.lists) {
@@ -103,7 +107,7 @@ void ncc_blocks(stereo_batch_s& b) {
       if (b.engine == 2) {
         if (L.which[k] == 0)
           blocks = ncc_job_blocks(P, ncc_both_extent(P.h2_pitch, 0, P.D), 0, P.D,
-                                  ncc_dc(L, b.engine), 4);
+                                  ncc_dc(b, L), 4);
       } else if (L.which[k] == 0) {
         blocks = ncc_job_blocks(P, P.W + P.D - 1, 0, P.D, L.dc, 1);
       }
@@ -352,7 +356,7 @@ stereo_status enqueue(stereo_batch_s& b, hipStream_t s, hipEvent_t* ev = nullptr
                                s), "batch statistics");
         break;
       case JK_NCC:
-        BHIP(launch_ncc_jobs(L.r, L.dt, b.engine == 2 ? 4 : 1, ncc_dc(L, b.engine),
+        BHIP(launch_ncc_jobs(L.r, L.dt, b.engine == 2 ? 4 : 1, ncc_dc(b, L),
                              static_cast<const NccJob*>(jobs), first, nj, blocks, s),
              "batch ncc");
         break;
@@ -464,6 +468,14 @@ stereo_status stereo_batch_set_tuning(stereo_batch_t b, const char* key, int32_t
       build_layout(*b);                 // the same sizes and offsets, another tile order
       b->bound_ws = nullptr;            // tables are uploaded again
     }
+  } else if (k == "ncc_levels") {
+    BREQ(value == 0 || value == 16 || value == 32 || value == 64,
+         "ncc_levels must be 0 (automatic), 16, 32 or 64");
+    if (value != b->ncc_levels) {
+      b->ncc_levels = value;
+      ncc_blocks(*b);                   // block counts of the NCC job lists
+      b->bound_ws = nullptr;            // tables are uploaded again
+    }
   } else if (k == "agg_engine") {
     BREQ(value >= 0 && value <= 2,
          "agg_engine must be 0 (vector ALU), 1 (matrix cores, FP32 operands) or 2 (matrix "
@@ -482,6 +494,7 @@ stereo_status stereo_batch_get_tuning(stereo_batch_t b, const char* key, int32_t
   const std::string k(key);
   if (k == "wg_per_cu") *value = b->wg_per_cu;
   else if (k == "tile_band") *value = b->tile_band;
+  else if (k == "ncc_levels") *value = b->ncc_levels;
   else if (k == "agg_levels_u8") *value = b->levels_u8;
   else if (k == "agg_levels_f32") *value = b->levels_f32;
   else if (k == "agg_engine") *value = b->engine;

@@ -267,6 +267,19 @@ hipError_t launch_ncc_jobs(int r, stereo_dtype dt, int quad, int dc, const NccJo
                            const int* first, int n, int blocks, hipStream_t s);
 hipError_t launch_lr_jobs(const LrJob* jobs, const int* first, int n, int blocks,
                           hipStream_t s);
+// Per-radius NCC instantiation units (k_ncc_rN.hip): launch_ncc and
+// launch_ncc_jobs dispatch on the plan's radius to these.
+#define STEREO_NCC_UNIT(N)                                                                     \
+  hipError_t launch_ncc_r##N(const Plan& P, const void* ref, const float* tar_w,              \
+                             const float* zX, const float* isdX, const float* zY,            \
+                             const float* isdY, float* C, int out_w, int64_t out_pitch,      \
+                             int64_t out_slice, int anchor, int d_first, int d_end,          \
+                             int quad, int pad, hipStream_t s, float* C2);                   \
+  hipError_t launch_ncc_jobs_r##N(stereo_dtype dt, int quad, int dc, const NccJob* jobs,     \
+                                  const int* first, int n, int blocks, hipStream_t s);
+STEREO_NCC_UNIT(1) STEREO_NCC_UNIT(2) STEREO_NCC_UNIT(3) STEREO_NCC_UNIT(4)
+STEREO_NCC_UNIT(5) STEREO_NCC_UNIT(6) STEREO_NCC_UNIT(7) STEREO_NCC_UNIT(8)
+#undef STEREO_NCC_UNIT
 
 // Grad workspace layout for the plan (sets g_off / g_end); 0 for U8 plans.
 size_t grad_layout(Plan& P, size_t base);

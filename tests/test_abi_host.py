@@ -129,6 +129,30 @@ def test_tuning_keys(lib):
     lib.stereo_plan_destroy(h)
 
 
+def test_batch_tuning_keys(lib):
+    # batch creation is host only: the item pointers are stored, never read
+    p = make_params(64, 48, 16, delta_p=8, plane=(4, 0, 0.1))
+    s, h = _create(lib, p)
+    items = (_lib.BatchItem * 1)()
+    items[0].plan = h.value
+    for f in ("ref", "tar", "dint_R", "valid", "disp"):
+        setattr(items[0], f, 4096)
+    b = ctypes.c_void_p()
+    assert lib.stereo_batch_create(items, 1, ctypes.byref(b)) == 0
+    v = ctypes.c_int32()
+    assert lib.stereo_batch_get_tuning(b, b"ncc_levels", ctypes.byref(v)) == 0 and v.value == 0
+    for nl in (16, 32, 64, 0):
+        assert lib.stereo_batch_set_tuning(b, b"ncc_levels", nl) == 0
+        assert lib.stereo_batch_get_tuning(b, b"ncc_levels", ctypes.byref(v)) == 0
+        assert v.value == nl
+    assert lib.stereo_batch_set_tuning(b, b"ncc_levels", 48) == 1
+    assert lib.stereo_batch_get_tuning(b, b"tile_band", ctypes.byref(v)) == 0 and v.value == 4
+    assert lib.stereo_batch_set_tuning(b, b"tile_band", 3) == 1
+    assert lib.stereo_batch_set_tuning(b, b"no_such_key", 8) == 1
+    lib.stereo_batch_destroy(b)
+    lib.stereo_plan_destroy(h)
+
+
 def test_volume_size_limit(lib):
     p = make_params(8192, 8192, 256, delta_p=8, plane=(4, 0, 0.1))
     assert _create(lib, p)[0] == 2
