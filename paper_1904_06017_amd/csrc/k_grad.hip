@@ -115,6 +115,11 @@ __global__ void __launch_bounds__(256) absmax_kernel(const float* __restrict__ g
   if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(out, __float_as_uint(m));
 }
 
+// Both passes read the levels of a thread in chunks of NA_CH: every load of
+// a chunk is issued (unconditionally; the flat-block rule selects after the
+// load) before the first use, so a thread waits once per chunk.
+constexpr int NA_CH = 8;
+
 __global__ void __launch_bounds__(kT)
 ncc_coef_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
                 const float* __restrict__ muX, const float* __restrict__ isdX,
@@ -130,21 +135,31 @@ ncc_coef_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
   const float iX = isdX[ro + x + r];
   const float mX = muX[ro + x + r];
   float sb = Sb[p], sbm = SbmX[p], sam = SamY[p];
-#pragma unroll 4
-  for (int t = 0; t < nlev; ++t) {
-    const int d = d_first + t;
-    const int cy = max(x - d, -r) + r;
-    const float iY = isdY[ro + cy];
-    const float mY = muY[ro + cy];
-    const bool flat = (iX == 0.0f) || (iY == 0.0f);
-    const float A = flat ? 0.0f : -gCt[t * HW + p] * inv_n;
-    const float rho = 1.0f - Ct[t * HW + p];
-    const float al = A * iX * iY;
-    const float be = A * rho * iX * iX;
-    Fa[t * HW + p] = al;
-    sb += be;
-    sbm = fmaf(be, mX, sbm);
-    sam = fmaf(al, mY, sam);
+  for (int t0 = 0; t0 < nlev; t0 += NA_CH) {
+    float iY[NA_CH], mY[NA_CH], g[NA_CH], c[NA_CH];
+#pragma unroll
+    for (int k = 0; k < NA_CH; ++k) {
+      const int t = min(t0 + k, nlev - 1);
+      const int cy = max(x - (d_first + t), -r) + r;
+      iY[k] = isdY[ro + cy];
+      mY[k] = muY[ro + cy];
+      g[k] = gCt[t * HW + p];
+      c[k] = Ct[t * HW + p];
+    }
+#pragma unroll
+    for (int k = 0; k < NA_CH; ++k) {
+      const int t = t0 + k;
+      const bool ok = t < nlev;
+      const bool flat = (iX == 0.0f) || (iY[k] == 0.0f);
+      const float A = flat ? 0.0f : -g[k] * inv_n;
+      const float rho = 1.0f - c[k];
+      const float al = A * iX * iY[k];
+      const float be = A * rho * iX * iX;
+      sb = ok ? sb + be : sb;
+      sbm = ok ? fmaf(be, mX, sbm) : sbm;
+      sam = ok ? fmaf(al, mY[k], sam) : sam;
+      if (ok) Fa[t * HW + p] = al;
+    }
   }
   Sb[p] = sb;
   SbmX[p] = sbm;
@@ -169,38 +184,169 @@ ncc_shear_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
   const float mY = muY[ro + cy];
   const int64_t q = (int64_t)y * WY + mi;
   float sax = SaX[q], sg = Sg[q];
-  // branch-free (clamped columns, results selected): the loads of several
-  // levels are in flight together
-#pragma unroll 8
-  for (int t = 0; t < nlev; ++t) {
-    const int x = m + d_first + t;
-    const bool ok = x >= 0 && x < W;
-    const int xc = min(max(x, 0), W - 1);
-    const float iX = isdX[ro + xc + r];
-    const float mX = muX[ro + xc + r];
-    const int64_t p = (int64_t)y * W + xc;
-    const bool flat = (iX == 0.0f) || (iY == 0.0f);
-    const float A = flat ? 0.0f : -gCt[t * HW + p] * inv_n;
-    const float rho = 1.0f - Ct[t * HW + p];
-    sax = ok ? fmaf(A * iX * iY, mX, sax) : sax;
-    sg = ok ? fmaf(A * rho, iY * iY, sg) : sg;
+  // clamped columns, results selected
+  for (int t0 = 0; t0 < nlev; t0 += NA_CH) {
+    float iX[NA_CH], mX[NA_CH], g[NA_CH], c[NA_CH];
+#pragma unroll
+    for (int k = 0; k < NA_CH; ++k) {
+      const int t = min(t0 + k, nlev - 1);
+      const int xc = min(max(m + d_first + t, 0), W - 1);
+      const int64_t p = (int64_t)y * W + xc;
+      iX[k] = isdX[ro + xc + r];
+      mX[k] = muX[ro + xc + r];
+      g[k] = gCt[t * HW + p];
+      c[k] = Ct[t * HW + p];
+    }
+#pragma unroll
+    for (int k = 0; k < NA_CH; ++k) {
+      const int t = t0 + k;
+      const int x = m + d_first + t;
+      const bool ok = t < nlev && x >= 0 && x < W;
+      const bool flat = (iX[k] == 0.0f) || (iY == 0.0f);
+      const float A = flat ? 0.0f : -g[k] * inv_n;
+      const float rho = 1.0f - c[k];
+      sax = ok ? fmaf(A * iX[k] * iY, mX[k], sax) : sax;
+      sg = ok ? fmaf(A * rho, iY * iY, sg) : sg;
+    }
   }
   SaX[q] = sax;
   Sg[q] = sg;
   SgY[q] = sg * mY;
 }
 
+// ncc_coef and ncc_shear in one pass (level tiles of at most 64 levels): a
+// wave covers pixels x = 64 bx + lane of row y, reads C and dC once, writes
+// alpha and the per-pixel sums as ncc_coef does, and forms the target-side
+// sums of column m = x - d along the diagonals: the partial sums of SaX and Sg
+// move one lane up per level (DPP wave shift; the one leaving lane 63 is
+// complete), so that local index U holds column m = 64 bx - d_first -
+// (nlev - 1) + U.  U >= nlev - 1 are this wave's own columns (added to the
+// maps); U < nlev - 1 also take levels of the next wave's pixels and go to
+// spill[y][bx][U][2] for ncc_adjoint_merge_kernel (one spill per column,
+// fixed order).  Products and their order per term are those of the two
+// separate passes.
+__device__ __forceinline__ float wave_shr1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+      0, __builtin_bit_cast(int, v), 0x138 /* wave_shr:1 */, 0xF, 0xF, false));
+}
+
+__global__ void __launch_bounds__(64)
+ncc_adjoint_kernel(const float* __restrict__ Ct, const float* __restrict__ gCt,
+                   const float* __restrict__ muX, const float* __restrict__ isdX,
+                   const float* __restrict__ muY, const float* __restrict__ isdY, int W, int H,
+                   int D, int r, int d_first, int nlev, float inv_n, float* __restrict__ Fa,
+                   float* __restrict__ Sb, float* __restrict__ SbmX, float* __restrict__ SamY,
+                   float* __restrict__ SaX, float* __restrict__ Sg,
+                   float* __restrict__ spill) {
+  __shared__ float fin[2][128];
+  const int lane = threadIdx.x, bx = blockIdx.x, y = blockIdx.y;
+  const int x = 64 * bx + lane;
+  const bool in = x < W;
+  const int xc = min(x, W - 1);
+  const int64_t HW = (int64_t)W * H;
+  const int64_t p = (int64_t)y * W + xc;
+  const int SW = W + 2 * r, WY = W + D - 1;
+  const int64_t ro = (int64_t)y * SW;
+  const float iX = isdX[ro + xc + r];
+  const float mX = muX[ro + xc + r];
+  float sb = Sb[p], sbm = SbmX[p], sam = SamY[p];
+  float dax = 0.0f, dg = 0.0f;                      // diagonal partial sums
+  for (int t0 = 0; t0 < nlev; t0 += NA_CH) {
+    float iY[NA_CH], mY[NA_CH], g[NA_CH], c[NA_CH];
+#pragma unroll
+    for (int k = 0; k < NA_CH; ++k) {
+      const int t = min(t0 + k, nlev - 1);
+      const int cy = max(xc - (d_first + t), -r) + r;
+      iY[k] = isdY[ro + cy];
+      mY[k] = muY[ro + cy];
+      g[k] = gCt[t * HW + p];
+      c[k] = Ct[t * HW + p];
+    }
+#pragma unroll
+    for (int k = 0; k < NA_CH; ++k) {
+      const int t = t0 + k;
+      if (t >= nlev) break;                         // uniform
+      const bool flat = (iX == 0.0f) || (iY[k] == 0.0f);
+      const float A = flat ? 0.0f : -g[k] * inv_n;
+      const float rho = 1.0f - c[k];
+      const float al = A * iX * iY[k];
+      const float Ar = A * rho;
+      const float be = Ar * iX * iX;
+      sb = in ? sb + be : sb;
+      sbm = in ? fmaf(be, mX, sbm) : sbm;
+      sam = in ? fmaf(al, mY[k], sam) : sam;
+      if (in) Fa[t * HW + p] = al;
+      if (t > 0) {
+        if (lane == 63) {                           // complete: no later level reaches it
+          fin[0][63 + nlev - t] = dax;
+          fin[1][63 + nlev - t] = dg;
+        }
+        dax = wave_shr1(dax);
+        dg = wave_shr1(dg);
+      }
+      dax = in ? fmaf(al, mX, dax) : dax;
+      dg = in ? fmaf(Ar, iY[k] * iY[k], dg) : dg;
+    }
+  }
+  if (in) {
+    Sb[p] = sb;
+    SbmX[p] = sbm;
+    SamY[p] = sam;
+  }
+  fin[0][lane] = dax;
+  fin[1][lane] = dg;
+  __syncthreads();
+  const int mi = 64 * bx + lane - d_first + D - 1;  // own index U = lane + nlev - 1
+  if (mi < WY) {
+    const int64_t q = (int64_t)y * WY + mi;
+    SaX[q] += fin[0][lane + nlev - 1];
+    Sg[q] += fin[1][lane + nlev - 1];
+  }
+  if (lane < nlev - 1) {
+    float* sp = spill + (((int64_t)y * gridDim.x + bx) * 64 + lane) * 2;
+    sp[0] = fin[0][lane];
+    sp[1] = fin[1][lane];
+  }
+}
+
+// Adds the spills of ncc_adjoint_kernel (column m of local index U < nlev - 1
+// of wave bx) and sets SgY = Sg muY for every column.
+__global__ void __launch_bounds__(kT)
+ncc_adjoint_merge_kernel(const float* __restrict__ spill, int nbx, int W, int D, int r,
+                         int d_first, int nlev, const float* __restrict__ muY,
+                         float* __restrict__ SaX, float* __restrict__ Sg,
+                         float* __restrict__ SgY) {
+  const int WY = W + D - 1;
+  const int mi = blockIdx.x * kT + threadIdx.x, y = blockIdx.y;
+  if (mi >= WY) return;
+  const int m = mi - (D - 1);
+  const int64_t q = (int64_t)y * WY + mi;
+  float sg = Sg[q];
+  const int u64 = m + d_first + nlev - 1;           // 64 bx + U
+  if (u64 >= 0) {
+    const int bx = u64 >> 6, u = u64 & 63;
+    if (u < nlev - 1 && bx < nbx) {
+      const float* sp = spill + (((int64_t)y * nbx + bx) * 64 + u) * 2;
+      SaX[q] += sp[0];
+      sg += sp[1];
+      Sg[q] = sg;
+    }
+  }
+  SgY[q] = sg * muY[(int64_t)y * (W + 2 * r) + max(m, -r) + r];
+}
+
 // Box sums onto a virtual domain: B(j) = sum_{o in [-r,r]^2} F(j - o) over
 // image pixels j - o (F is [H][W], B is [H + 2r][W + 2r], virtual position j
-// at index j + r).  A workgroup (one wave) covers BX_TX virtual columns x
-// BX_TY virtual rows of one map: the (BX_TY + 2r) x (BX_TX + 2r) input tile,
-// zero outside the image, is staged in LDS; each lane walks down its column
-// with a ring of 2r+1 horizontal sums (fixed order: horizontal j = -r..r,
-// then vertical i = -r..r).  grid.z indexes the maps.
-constexpr int BX_TX = 64, BX_TY = 32;
+// at index j + r).  A workgroup (BX_TX / 64 waves) covers BX_TX virtual
+// columns x BX_TY virtual rows of one map: the (BX_TY + 2r) x (BX_TX + 2r)
+// input tile, zero outside the image, is staged in LDS (clamped loads, all
+// issued before the first LDS store); each lane walks down its column with
+// a ring of 2r+1 horizontal sums (fixed order: horizontal j = -r..r, then
+// vertical i = -r..r).  grid.z indexes the maps.
+constexpr int BX_TX = 256, BX_TY = 32;
 
 template <int r>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(BX_TX)
 box_kernel(const float* __restrict__ F, int W, int H, float* __restrict__ B) {
   constexpr int K = 2 * r + 1;
   constexpr int TWI = BX_TX + 2 * r, THI = BX_TY + 2 * r;
@@ -212,21 +358,20 @@ box_kernel(const float* __restrict__ F, int W, int H, float* __restrict__ B) {
   const int vx0 = blockIdx.x * BX_TX - r;          // first virtual column (image coords)
   const int vy0 = blockIdx.y * BX_TY - r;          // first virtual row (image coords)
   const int ix0 = vx0 - r, iy0 = vy0 - r;          // first input column / row
-  // every load of the lane is issued before the first store to LDS: a single
-  // wave per workgroup needs the whole tile in flight to cover HBM latency
-  constexpr int NL = (THI * TWI + 63) / 64;
+  constexpr int NL = (THI * TWI + BX_TX - 1) / BX_TX;
   float v[NL];
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
-    const int i = threadIdx.x + 64 * k;
+    const int i = min((int)threadIdx.x + BX_TX * k, THI * TWI - 1);
     const int yy = i / TWI, xx = i - yy * TWI;
     const int iy = iy0 + yy, ix = ix0 + xx;
-    v[k] = (i < THI * TWI && iy >= 0 && iy < H && ix >= 0 && ix < W) ? f[(int64_t)iy * W + ix]
-                                                                      : 0.0f;
+    const bool in = iy >= 0 && iy < H && ix >= 0 && ix < W;
+    const float val = f[(int64_t)clampi(iy, 0, H - 1) * W + clampi(ix, 0, W - 1)];
+    v[k] = in ? val : 0.0f;
   }
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
-    const int i = threadIdx.x + 64 * k;
+    const int i = threadIdx.x + BX_TX * k;
     if (i < THI * TWI) tile[i] = v[k];
   }
   __syncthreads();
@@ -297,6 +442,82 @@ assemble_y_kernel(const float* __restrict__ Ba, const T* __restrict__ ref, int64
     acc = fmaf(xv, Ba[j], acc);
   }
   gYv[(int64_t)vy * WVY + ky] += acc;
+}
+
+// Both sides from one read of the boxes of alpha (levels d = d_first + t of
+// one level tile, t < nlev <= 64):
+//   gXv(j) += sum_t Yv(j - d) B_alpha,t(j)            (per virtual X column)
+//   gYv(k) += sum_t Xv(k + d) B_alpha,t(k + d)        (along the diagonals)
+// with the products and their order those of assemble_x / assemble_y.  A
+// wave covers the virtual X columns j = 64 bx + lane of virtual row vy.  The
+// target sum of local index U (Y-domain column 64 bx + D - 1 - d_first -
+// (nlev - 1) + U) takes lane U - (nlev - 1 - t) at level t: the partial sums
+// move one lane up per level (DPP wave shift), and the one leaving lane 63 is
+// complete (kept in LDS).  Indices U >= nlev - 1 are this wave's own columns
+// (added to gYv); U < nlev - 1 also take levels of the next wave's columns:
+// they go to spill[vy][bx][U], which assemble_merge_kernel adds afterwards
+// (one spill per column: deterministic).
+constexpr int AS_CH = 8;
+
+template <typename T>
+__global__ void __launch_bounds__(64)
+assemble_kernel(const float* __restrict__ Ba, const float* __restrict__ tarw,
+                const T* __restrict__ ref, int64_t rpitch, int W, int H, int D, int r,
+                int d_first, int nlev, float* __restrict__ gXv, float* __restrict__ gYv,
+                float* __restrict__ spill) {
+  __shared__ float fin[128];
+  const int WV = W + 2 * r, HV = H + 2 * r, WVY = W + D - 1 + 2 * r;
+  const int lane = threadIdx.x, bx = blockIdx.x, vy = blockIdx.y;
+  const int vx = 64 * bx + lane;
+  const bool in = vx < WV;
+  const int64_t HVWV = (int64_t)HV * WV;
+  const int y = clampi(vy - r, 0, H - 1);
+  const float* trow = tarw + (int64_t)y * W;
+  const float* brow = Ba + (int64_t)vy * WV + min(vx, WV - 1);
+  const float xv = ldf(ref + (int64_t)y * rpitch + clampi(vx - r, 0, W - 1)) - kOffset;
+  float ax = 0.0f, ay = 0.0f;
+  for (int t0 = 0; t0 < nlev; t0 += AS_CH) {
+    float b[AS_CH], yv[AS_CH];
+#pragma unroll
+    for (int k = 0; k < AS_CH; ++k) {
+      const int t = min(t0 + k, nlev - 1);
+      b[k] = brow[t * HVWV];
+      yv[k] = trow[clampi(vx - r - (d_first + t), 0, W - 1)];
+    }
+#pragma unroll
+    for (int k = 0; k < AS_CH; ++k) {
+      const int t = t0 + k;
+      if (t >= nlev) break;                         // uniform
+      const float bb = in ? b[k] : 0.0f;
+      ax = fmaf(yv[k] - kOffset, bb, ax);
+      if (t > 0) {
+        if (lane == 63) fin[63 + nlev - t] = ay;    // complete: no later level reaches it
+        ay = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                 0, __builtin_bit_cast(int, ay), 0x138 /* wave_shr:1 */, 0xF, 0xF, false));
+      }
+      ay = fmaf(xv, bb, ay);
+    }
+  }
+  fin[lane] = ay;
+  __syncthreads();
+  if (in) gXv[(int64_t)vy * WV + vx] += ax;
+  const int ky = 64 * bx + lane + D - 1 - d_first;  // own index U = lane + nlev - 1
+  if (ky < WVY) gYv[(int64_t)vy * WVY + ky] += fin[lane + nlev - 1];
+  if (lane < nlev - 1) spill[((int64_t)vy * gridDim.x + bx) * 64 + lane] = fin[lane];
+}
+
+// gYv(k) += the spill of the wave whose local index U < nlev - 1 is k.
+__global__ void __launch_bounds__(kT)
+assemble_merge_kernel(const float* __restrict__ spill, int nbx, int W, int D, int r,
+                      int d_first, int nlev, float* __restrict__ gYv) {
+  const int WVY = W + D - 1 + 2 * r;
+  const int ky = blockIdx.x * kT + threadIdx.x, vy = blockIdx.y;
+  if (ky >= WVY) return;
+  const int q = ky - (D - 1) + d_first + (nlev - 1);    // 64 bx + U
+  if (q < 0) return;
+  const int bx = q >> 6, u = q & 63;
+  if (u >= nlev - 1 || bx >= nbx) return;
+  gYv[(int64_t)vy * WVY + ky] += spill[((int64_t)vy * nbx + bx) * 64 + u];
 }
 
 // Target side terms summed over all levels (virtual Y domain):
@@ -547,8 +768,10 @@ size_t grad_layout(Plan& P, size_t o) {
   for (int i = GR_WP; i <= GR_GTARW; ++i) sz[i] = f4 * HW;
   sz[GR_SUMS] = 3 * f4 * HW;
   for (int i = GR_CT; i <= GR_GCT; ++i) sz[i] = f4 * DT * HW;
-  sz[GR_FA] = f4 * DT * HW;
-  sz[GR_BA] = f4 * DT * HV * WVX;
+  // alpha maps, then the assemble pass's spills [HV][WVX / 64][64]
+  sz[GR_FA] = f4 * std::max((size_t)DT * HW, HV * ((WVX + 63) / 64) * 64);
+  // boxes of alpha; before them the NCC adjoint pass's spills [H][W / 64][64][2]
+  sz[GR_BA] = f4 * std::max((size_t)DT * HV * WVX, (size_t)P.H * ((P.W + 63) / 64) * 128);
   sz[GR_BS] = 3 * f4 * HV * WVX;
   sz[GR_SY] = 3 * f4 * (size_t)P.H * (P.W + P.D - 1);
   sz[GR_BSY] = 3 * f4 * HV * WVY;
@@ -620,7 +843,7 @@ Maps maps_of(const Plan& P, void* ws) {
 template <int r>
 stereo_status box_r(int W, int H, const float* F, int nmaps, float* B, hipStream_t s) {
   dim3 grid((W + 2 * r + BX_TX - 1) / BX_TX, (H + 2 * r + BX_TY - 1) / BX_TY, nmaps);
-  LAUNCH("box sums", (box_kernel<r>), grid, dim3(64), 0, s, F, W, H, B);
+  LAUNCH("box sums", (box_kernel<r>), grid, dim3(BX_TX), 0, s, F, W, H, B);
   return STEREO_OK;
 }
 
@@ -852,16 +1075,38 @@ stereo_status stereo_backward_profiled(stereo_plan_t plan, const float* ref, con
     HIPC(launch_bilateral(P, a, 6, stream), "aggregation adjoint");
     if (d0 == 0) HIPC(mark(4), "event record");
     }
-    LAUNCH("ncc adjoint coefficients", ncc_coef_kernel, rows, dim3(kT), 0, stream, Ct, gCt,
-           muX, m.isdX, muY, m.isdY, W, H, r, d0, nl, 1.0f / (float)n, Fa, Sb, SbmX, SamY);
-    LAUNCH("ncc adjoint target sums", ncc_shear_kernel, dim3((WY + kT - 1) / kT, H), dim3(kT), 0,
-           stream, Ct, gCt, muX, m.isdX, muY, m.isdY, W, H, D, r, d0, nl, 1.0f / (float)n,
-           SaX, Sg, SgY);
+    if (nl <= 64) {
+      // both passes over C and dC in one; the boxes of alpha (written later)
+      // hold the spills until the merge
+      const int nbx = (W + 63) / 64;
+      LAUNCH("ncc adjoint (coefficients, diagonal sums)", ncc_adjoint_kernel, dim3(nbx, H),
+             dim3(64), 0, stream, Ct, gCt, muX, m.isdX, muY, m.isdY, W, H, D, r, d0, nl,
+             1.0f / (float)n, Fa, Sb, SbmX, SamY, SaX, Sg, Ba);
+      LAUNCH("ncc adjoint (diagonal spills)", ncc_adjoint_merge_kernel,
+             dim3((WY + kT - 1) / kT, H), dim3(kT), 0, stream, Ba, nbx, W, D, r, d0, nl, muY,
+             SaX, Sg, SgY);
+    } else {
+      LAUNCH("ncc adjoint coefficients", ncc_coef_kernel, rows, dim3(kT), 0, stream, Ct, gCt,
+             muX, m.isdX, muY, m.isdY, W, H, r, d0, nl, 1.0f / (float)n, Fa, Sb, SbmX, SamY);
+      LAUNCH("ncc adjoint target sums", ncc_shear_kernel, dim3((WY + kT - 1) / kT, H), dim3(kT),
+             0, stream, Ct, gCt, muX, m.isdX, muY, m.isdY, W, H, D, r, d0, nl,
+             1.0f / (float)n, SaX, Sg, SgY);
+    }
     if ((st = box(P, W, Fa, nl, Ba, stream)) != STEREO_OK) return st;
-    LAUNCH("ncc adjoint (reference side)", assemble_x_kernel, dim3((WVX + 255) / 256, HV),
-           dim3(256), 0, stream, Ba, tarw, W, H, r, d0, nl, gXv);
-    LAUNCH("ncc adjoint (target side)", assemble_y_kernel<float>, dim3((WVY + 255) / 256, HV),
-           dim3(256), 0, stream, Ba, ref, P.p.pitch_ref, W, H, D, r, d0, nl, gYv);
+    if (nl <= 64) {
+      // both sides in one pass over the boxes; the alpha maps are consumed,
+      // their region holds the spills
+      const int nbx = (WVX + 63) / 64;
+      LAUNCH("ncc adjoint (both sides)", assemble_kernel<float>, dim3(nbx, HV), dim3(64), 0,
+             stream, Ba, tarw, ref, P.p.pitch_ref, W, H, D, r, d0, nl, gXv, gYv, Fa);
+      LAUNCH("ncc adjoint (target spills)", assemble_merge_kernel,
+             dim3((WVY + kT - 1) / kT, HV), dim3(kT), 0, stream, Fa, nbx, W, D, r, d0, nl, gYv);
+    } else {
+      LAUNCH("ncc adjoint (reference side)", assemble_x_kernel, dim3((WVX + 255) / 256, HV),
+             dim3(256), 0, stream, Ba, tarw, W, H, r, d0, nl, gXv);
+      LAUNCH("ncc adjoint (target side)", assemble_y_kernel<float>, dim3((WVY + 255) / 256, HV),
+             dim3(256), 0, stream, Ba, ref, P.p.pitch_ref, W, H, D, r, d0, nl, gYv);
+    }
   }
   if ((st = box(P, W, SamY, 3, BS, stream)) != STEREO_OK) return st;
   LAUNCH("ncc adjoint (level sums)", x_complete_kernel<float>, dim3((WVX + 255) / 256, HV),
