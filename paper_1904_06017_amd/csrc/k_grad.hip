@@ -104,15 +104,31 @@ guide_finish_kernel(const GT* __restrict__ g, int64_t gpitch, const float* __res
 // and dC; one fused pass with the diagonals exchanged through LDS, or read
 // through the caches, measured slower).
 // max |g| over n values into *out (float bits; non-negative floats order as
-// their bits), one atomic per wave; *out is zeroed before the launch.
+// their bits), one atomic per workgroup (atomics on one address serialise);
+// *out is zeroed before the launch.  Four independent loads per thread and
+// round.
 __global__ void __launch_bounds__(256) absmax_kernel(const float* __restrict__ g, int64_t n,
                                                      unsigned int* __restrict__ out) {
+  __shared__ float wm[4];
   float m = 0.0f;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    m = fmaxf(m, fabsf(g[i]));
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += 4 * stride) {
+    float v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t i = i0 + k * stride;
+      v[k] = i < n ? fabsf(g[i]) : 0.0f;
+    }
+    m = fmaxf(m, fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
+  }
 #pragma unroll
   for (int k = 1; k < 64; k <<= 1) m = fmaxf(m, __shfl_xor(m, k));
-  if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(out, __float_as_uint(m));
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+    if (m > 0.0f) atomicMax(out, __float_as_uint(m));
+  }
 }
 
 // Both passes read the levels of a thread in chunks of NA_CH: every load of
@@ -673,11 +689,17 @@ struct ZeroList {
   int64_t n[kZeroMax];
 };
 
+// Four floats per thread (the regions start 256-byte aligned).
 __global__ void __launch_bounds__(kT)
 zero_many_kernel(ZeroList z) {
   const int k = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
-  if (i < z.n[k]) z.p[k][i] = 0.0f;
+  const int64_t i = 4 * ((int64_t)blockIdx.x * kT + threadIdx.x);
+  const int64_t n = z.n[k];
+  if (i + 4 <= n) {
+    *reinterpret_cast<float4*>(z.p[k] + i) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  } else {
+    for (int64_t j = i; j < n; ++j) z.p[k][j] = 0.0f;
+  }
 }
 
 // Block means mu = z / (1/sd) of both statistics maps (0 for flat blocks),
@@ -979,8 +1001,8 @@ stereo_status stereo_backward_profiled(stereo_plan_t plan, const float* ref, con
       z.n[k] = len[k];
       nmax = std::max(nmax, len[k]);
     }
-    LAUNCH("zero", zero_many_kernel, dim3((unsigned)((nmax + kT - 1) / kT), kZeroMax), dim3(kT),
-           0, stream, z);
+    LAUNCH("zero", zero_many_kernel, dim3((unsigned)((nmax + 4 * kT - 1) / (4 * kT)), kZeroMax),
+           dim3(kT), 0, stream, z);
   }
 
   // forward state that is cheap to rebuild: warp, block statistics
@@ -1003,7 +1025,9 @@ stereo_status stereo_backward_profiled(stereo_plan_t plan, const float* ref, con
   if (mc) {
     // max |g'| (the scale of C' in pass 1) and zeros in the pad columns of
     // the C' volume, which the passes never write
-    LAUNCH("max |g'|", absmax_kernel, dim3(240), dim3(256), 0, stream, grad_disp, HW,
+    LAUNCH("max |g'|", absmax_kernel,
+           dim3((unsigned)std::min<int64_t>(256, (HW + 1023) / 1024)), dim3(256), 0, stream,
+           grad_disp, HW,
            reinterpret_cast<unsigned int*>(R_(GR_GMAX)));
     HIPC(launch_h2_pad_zero(at<uint16_t>(ws, P.off_cvol + P.h2_tar_off),
                             16 * (int64_t)H * P.h2_pitch, P.h2_pitch, W, H, P.R, (DT + 15) / 16,

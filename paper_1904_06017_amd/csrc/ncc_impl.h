@@ -28,11 +28,12 @@ __device__ __forceinline__ float ld(const T* p) { return static_cast<float>(*p);
 // rows (z and 1/sd at the shifted block centres: one contiguous column range
 // per row) and the A side's at the lanes' own columns are staged in LDS with
 // clamped reads.  A wave's NC_DW levels read overlapping windows of the same
-// B row: one window of K + NC_DW - 1 values serves them all.  16-row tiles
-// redo 2r of every 16 + 2r input rows but need half the LDS of 32-row ones,
-// so twice the workgroups stay resident (1280x720, 64 levels, r = 3: 0.115
-// against 0.131 ms for both split volumes).
-constexpr int NC_TX = 64, NC_TY = 16, NC_DC = 16, NC_DW = 4;
+// B row: one window of K + NC_DW - 1 values serves them all.  8-row tiles
+// redo 2r of every 8 + 2r input rows but need a quarter of the LDS of
+// 32-row ones, so more workgroups stay resident to overlap the stores
+// (1280x720, 64 levels, r = 3, both split volumes: 0.111 ms against 0.113 /
+// 0.114 / 0.131 ms with 12- / 16- / 32-row tiles).
+constexpr int NC_TX = 64, NC_TY = 8, NC_DC = 16, NC_DW = 4;
 // NC_DC is the default level block; a workgroup of DC levels has DC / 4 waves.
 
 template <int r, int DC = NC_DC>
