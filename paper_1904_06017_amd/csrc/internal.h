@@ -232,6 +232,10 @@ struct NccJob {             // grid: gx = ceil(out_w / 64) x gy = ceil(H / 32) x
   int W, H, d_first, d_end, out_w, anchor, gx, gy;
   int pad;                    // split-FP16 output (quad = 2, 4): column shift
   float* C2;                  // quad = 4: the target-anchored volume (nullable)
+  // the kernel reaches C and C2 as byte offsets from the launch's base (a
+  // kernel argument, so the compiler knows the stores are global); c2_off
+  // < 0: no C2
+  int64_t c_off, c2_off;
 };
 struct LrJob {              // grid: gx = ceil(W / 256) x H rows
   const int16_t* dR; const int16_t* dT; const float* dsub; uint8_t* valid; float* disp;
@@ -253,7 +257,7 @@ StatsJob stats_job(const Plan& P, const void* img, int64_t pitch, float* z, floa
 NccJob ncc_job(const Plan& P, const void* ref, const float* tar_w, const float* zX,
                const float* isdX, const float* zY, const float* isdY, float* C, int out_w,
                int64_t out_pitch, int64_t out_slice, int anchor, int d_first, int d_end,
-               int quad, float* C2);
+               int quad, float* C2, const void* base);
 LrJob lr_job(const Plan& P, const int16_t* dR, const int16_t* dT, const float* dsub,
              uint8_t* valid, float* disp);
 // jobs / first are device arrays; dt is the element type of the job images
@@ -263,8 +267,9 @@ hipError_t launch_warp_jobs(stereo_dtype dt, const WarpJob* jobs, const int* fir
 hipError_t launch_stats_jobs(stereo_dtype dt, const StatsJob* jobs, const int* first, int n,
                              int blocks, int max_r, hipStream_t s);
 // dc: levels per workgroup (16, 32 or 64), the same for every job of the list
+// base: the allocation holding every job's C and C2 (their offsets)
 hipError_t launch_ncc_jobs(int r, stereo_dtype dt, int quad, int dc, const NccJob* jobs,
-                           const int* first, int n, int blocks, hipStream_t s);
+                           const int* first, int n, int blocks, char* base, hipStream_t s);
 hipError_t launch_lr_jobs(const LrJob* jobs, const int* first, int n, int blocks,
                           hipStream_t s);
 // Per-radius NCC instantiation units (k_ncc_rN.hip): launch_ncc and
@@ -276,7 +281,8 @@ hipError_t launch_lr_jobs(const LrJob* jobs, const int* first, int n, int blocks
                              int64_t out_slice, int anchor, int d_first, int d_end,          \
                              int quad, int pad, hipStream_t s, float* C2);                   \
   hipError_t launch_ncc_jobs_r##N(stereo_dtype dt, int quad, int dc, const NccJob* jobs,     \
-                                  const int* first, int n, int blocks, hipStream_t s);
+                                  const int* first, int n, int blocks, char* base,          \
+                                  hipStream_t s);
 STEREO_NCC_UNIT(1) STEREO_NCC_UNIT(2) STEREO_NCC_UNIT(3) STEREO_NCC_UNIT(4)
 STEREO_NCC_UNIT(5) STEREO_NCC_UNIT(6) STEREO_NCC_UNIT(7) STEREO_NCC_UNIT(8)
 #undef STEREO_NCC_UNIT

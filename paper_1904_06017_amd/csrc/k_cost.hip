@@ -247,9 +247,11 @@ StatsJob stats_job(const Plan& P, const void* img, int64_t pitch, float* z, floa
 NccJob ncc_job(const Plan& P, const void* ref, const float* tar_w, const float* zX,
                const float* isdX, const float* zY, const float* isdY, float* C, int out_w,
                int64_t out_pitch, int64_t out_slice, int anchor, int d_first, int d_end,
-               int quad, float* C2) {
+               int quad, float* C2, const void* base) {
   NccJob J{};
   J.C2 = C2;
+  J.c_off = reinterpret_cast<const char*>(C) - static_cast<const char*>(base);
+  J.c2_off = C2 ? reinterpret_cast<const char*>(C2) - static_cast<const char*>(base) : -1;
   J.ref = ref; J.ref_pitch = P.p.pitch_ref; J.tarw = tar_w;
   J.zX = zX; J.isdX = isdX; J.zY = zY; J.isdY = isdY;
   J.C = C; J.out_pitch = out_pitch; J.out_slice = out_slice;
@@ -284,17 +286,17 @@ hipError_t launch_stats_jobs(stereo_dtype dt, const StatsJob* jobs, const int* f
 
 
 hipError_t launch_ncc_jobs(int r, stereo_dtype dt, int quad, int dc, const NccJob* jobs,
-                           const int* first, int n, int blocks, hipStream_t s) {
+                           const int* first, int n, int blocks, char* base, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   switch (r) {
-    case 1: return launch_ncc_jobs_r1(dt, quad, dc, jobs, first, n, blocks, s);
-    case 2: return launch_ncc_jobs_r2(dt, quad, dc, jobs, first, n, blocks, s);
-    case 3: return launch_ncc_jobs_r3(dt, quad, dc, jobs, first, n, blocks, s);
-    case 4: return launch_ncc_jobs_r4(dt, quad, dc, jobs, first, n, blocks, s);
-    case 5: return launch_ncc_jobs_r5(dt, quad, dc, jobs, first, n, blocks, s);
-    case 6: return launch_ncc_jobs_r6(dt, quad, dc, jobs, first, n, blocks, s);
-    case 7: return launch_ncc_jobs_r7(dt, quad, dc, jobs, first, n, blocks, s);
-    case 8: return launch_ncc_jobs_r8(dt, quad, dc, jobs, first, n, blocks, s);
+    case 1: return launch_ncc_jobs_r1(dt, quad, dc, jobs, first, n, blocks, base, s);
+    case 2: return launch_ncc_jobs_r2(dt, quad, dc, jobs, first, n, blocks, base, s);
+    case 3: return launch_ncc_jobs_r3(dt, quad, dc, jobs, first, n, blocks, base, s);
+    case 4: return launch_ncc_jobs_r4(dt, quad, dc, jobs, first, n, blocks, base, s);
+    case 5: return launch_ncc_jobs_r5(dt, quad, dc, jobs, first, n, blocks, base, s);
+    case 6: return launch_ncc_jobs_r6(dt, quad, dc, jobs, first, n, blocks, base, s);
+    case 7: return launch_ncc_jobs_r7(dt, quad, dc, jobs, first, n, blocks, base, s);
+    case 8: return launch_ncc_jobs_r8(dt, quad, dc, jobs, first, n, blocks, base, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -14,8 +14,8 @@ hipError_t launch_ncc_r7(const Plan& P, const void* ref, const float* tar_w, con
                                  out_pitch, out_slice, anchor, d_first, d_end, quad, pad, s, C2);
 }
 hipError_t launch_ncc_jobs_r7(stereo_dtype dt, int quad, int dc, const NccJob* jobs,
-                              const int* first, int n, int blocks, hipStream_t s) {
-  if (dt == STEREO_U8) return ncc_jobs_r<7, uint8_t>(quad, dc, jobs, first, n, blocks, s);
-  return ncc_jobs_r<7, float>(quad, dc, jobs, first, n, blocks, s);
+                              const int* first, int n, int blocks, char* base, hipStream_t s) {
+  if (dt == STEREO_U8) return ncc_jobs_r<7, uint8_t>(quad, dc, jobs, first, n, blocks, base, s);
+  return ncc_jobs_r<7, float>(quad, dc, jobs, first, n, blocks, base, s);
 }
 }  // namespace stereo

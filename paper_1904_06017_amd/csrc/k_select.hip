@@ -114,13 +114,19 @@ lr_tracked_kernel(const int16_t* __restrict__ dR, const int16_t* __restrict__ dT
           st->plane[2], valid, disp, blockIdx.x, blockIdx.y);
 }
 
+// Job index of a block of a batched launch: the jobs whose first block is at
+// or before b, counted 64 at a time by one load per lane and a ballot (every
+// lane of the wave calls it; first[] is the ascending block prefix).
 __device__ __forceinline__ int job_of(const int* __restrict__ first, int n, int b) {
-  int lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (first[mid] <= b) lo = mid; else hi = mid;
+  int cnt = 0;
+  for (int c = 0; c < n; c += 64) {
+    const int k = c + (int)(threadIdx.x & 63);
+    const bool le = k < n && first[min(k, n - 1)] <= b;
+    const int add = __popcll(__ballot(le));
+    cnt += add;
+    if (add < 64) break;
   }
-  return lo;
+  return cnt - 1;
 }
 
 __global__ void __launch_bounds__(256)

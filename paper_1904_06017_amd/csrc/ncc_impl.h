@@ -13,6 +13,17 @@ namespace {
 template <typename T>
 __device__ __forceinline__ float ld(const T* p) { return static_cast<float>(*p); }
 
+// Staging loads of the NCC body through the global address space: its
+// pointers may come from a job descriptor in memory, which the compiler
+// would reach with flat instructions (flat operations also count against
+// the LDS wait counter).  The batched kernel forms its output pointers from
+// a kernel argument, which the compiler knows to be global.
+#define NCC_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ float gld(const T* p) {
+  return static_cast<float>(*(const NCC_GLOBAL T*)p);
+}
+
 // NCC cost, Eq. (8), in its equivalent 1 - NCC form on offset intensities:
 //   C = 1 - (S/n - muX muY) / (sdX sdY) = 1 + zX zY - (S/n) isdX isdY,
 // S = sum over the block of X' Y', z = mu / sd, isd = 1 / sd.
@@ -177,8 +188,8 @@ __device__ __forceinline__ void ncc_body_a(const T* __restrict__ ref, int64_t re
     const int gy = min(max(y0 - r + yy, 0), H - 1);
     const int gxb = min(max(bxo + xx, 0), W - 1);
     const int gxa = min(max(axo + min(xx, G::AW - 1), 0), W - 1);
-    return anchor ? make_float2(ld(ref + (int64_t)gy * ref_pitch + gxb), tarw[(int64_t)gy * W + gxa])
-                  : make_float2(tarw[(int64_t)gy * W + gxb], ld(ref + (int64_t)gy * ref_pitch + gxa));
+    return anchor ? make_float2(gld(ref + (int64_t)gy * ref_pitch + gxb), gld(tarw + (int64_t)gy * W + gxa))
+                  : make_float2(gld(tarw + (int64_t)gy * W + gxb), gld(ref + (int64_t)gy * ref_pitch + gxa));
   }, [&](int i, float2 v) {
     const int yy = i / G::BW, xx = i - yy * G::BW;
     Bs[i] = v.x - kOffset;
@@ -191,7 +202,7 @@ __device__ __forceinline__ void ncc_body_a(const T* __restrict__ ref, int64_t re
     const int t = i / G::ZW, c = i - t * G::ZW;
     const int64_t rowo = (int64_t)min(y0 + t, H - 1) * SW;
     const int cb = min(max(zxo + c, -r), W - 1 + r) + r;
-    return make_float2(zm[rowo + cb], im[rowo + cb]);
+    return make_float2(gld(zm + rowo + cb), gld(im + rowo + cb));
   }, [&](int i, float2 v) { Zs[i] = v.x; Is[i] = v.y; });
   // A-side statistics of each lane's own column (in LDS, so that the row
   // loop issues no global loads: their wait would also wait for the previous
@@ -200,7 +211,7 @@ __device__ __forceinline__ void ncc_body_a(const T* __restrict__ ref, int64_t re
     const int t = i / NC_TX, c = i - t * NC_TX;
     const int64_t rowo = (int64_t)min(y0 + t, H - 1) * SW;
     const int cb = min(max(x0 + c, -r), W - 1 + r) + r;
-    return make_float2(za[rowo + cb], ia[rowo + cb]);
+    return make_float2(gld(za + rowo + cb), gld(ia + rowo + cb));
   }, [&](int i, float2 v) { ZA[i] = v.x; IA[i] = v.y * inv_n; });
   __syncthreads();
 
@@ -360,28 +371,36 @@ ncc_kernel(const T* __restrict__ ref, int64_t ref_pitch,
 }
 
 
-// Job index of a block of a batched launch (binary search of the prefix).
+// Job index of a block of a batched launch: the jobs whose first block is at
+// or before b, counted 64 at a time by one load per lane and a ballot (every
+// lane of the wave calls it; first[] is the ascending block prefix).
 __device__ __forceinline__ int job_of(const int* __restrict__ first, int n, int b) {
-  int lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (first[mid] <= b) lo = mid; else hi = mid;
+  int cnt = 0;
+  for (int c = 0; c < n; c += 64) {
+    const int k = c + (int)(threadIdx.x & 63);
+    const bool le = k < n && first[min(k, n - 1)] <= b;
+    const int add = __popcll(__ballot(le));
+    cnt += add;
+    if (add < 64) break;
   }
-  return lo;
+  return cnt - 1;
 }
 
 template <int r, typename T, int QUAD, int DC>
 __global__ void __launch_bounds__(16 * DC)
-ncc_jobs_kernel(const NccJob* __restrict__ jobs, const int* __restrict__ first, int n) {
+ncc_jobs_kernel(const NccJob* __restrict__ jobs, const int* __restrict__ first, int n,
+                char* __restrict__ base) {
   extern __shared__ float sm[];
   const int j = job_of(first, n, blockIdx.x);
   const NccJob& J = jobs[j];
   const int l = blockIdx.x - first[j];
   const int gxy = J.gx * J.gy;
   const int bz = l / gxy, rem = l - bz * gxy;
+  float* C = reinterpret_cast<float*>(base + J.c_off);
+  float* C2 = J.c2_off >= 0 ? reinterpret_cast<float*>(base + J.c2_off) : nullptr;
   ncc_body<r, T, QUAD, DC>(static_cast<const T*>(J.ref), J.ref_pitch, J.tarw, J.W, J.H, J.d_first,
-                       J.d_end, J.zX, J.isdX, J.zY, J.isdY, J.C, J.out_w, J.out_pitch,
-                       J.out_slice, J.anchor, J.pad, sm, rem % J.gx, rem / J.gx, bz, J.C2);
+                       J.d_end, J.zX, J.isdX, J.zY, J.isdY, C, J.out_w, J.out_pitch,
+                       J.out_slice, J.anchor, J.pad, sm, rem % J.gx, rem / J.gx, bz, C2);
 }
 
 // Dynamic LDS above the 64 KB default (large radii at 64 levels), set once
@@ -486,32 +505,32 @@ hipError_t launch_ncc_r(const Plan& P, const T* ref, const float* tar_w, const f
 
 template <int r, typename T, int DC>
 hipError_t ncc_jobs_rdc(int quad, const NccJob* jobs, const int* first, int n, int blocks,
-                        hipStream_t s) {
+                        char* base, hipStream_t s) {
   hipError_t e = quad == 4 ? ncc_allow_lds<r, T, 4, DC, 1>()
                  : quad == 2 ? ncc_allow_lds<r, T, 2, DC, 1>()
                  : quad ? ncc_allow_lds<r, T, 1, DC, 1>() : ncc_allow_lds<r, T, 0, DC, 1>();
   if (e != hipSuccess) return e;
   if (quad == 4)
     hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 4, DC>), dim3(blocks), dim3(16 * DC),
-                       (NccGeom<r, DC>::lds_bytes), s, jobs, first, n);
+                       (NccGeom<r, DC>::lds_bytes), s, jobs, first, n, base);
   else if (quad == 2)
     hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 2, DC>), dim3(blocks), dim3(16 * DC),
-                       (NccGeom<r, DC>::lds_bytes), s, jobs, first, n);
+                       (NccGeom<r, DC>::lds_bytes), s, jobs, first, n, base);
   else if (quad)
     hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 1, DC>), dim3(blocks), dim3(16 * DC),
-                       (NccGeom<r, DC>::lds_bytes), s, jobs, first, n);
+                       (NccGeom<r, DC>::lds_bytes), s, jobs, first, n, base);
   else
     hipLaunchKernelGGL((ncc_jobs_kernel<r, T, 0, DC>), dim3(blocks), dim3(16 * DC),
-                       (NccGeom<r, DC>::lds_bytes), s, jobs, first, n);
+                       (NccGeom<r, DC>::lds_bytes), s, jobs, first, n, base);
   return hipGetLastError();
 }
 template <int r, typename T>
 hipError_t ncc_jobs_r(int quad, int dc, const NccJob* jobs, const int* first, int n, int blocks,
-                      hipStream_t s) {
+                      char* base, hipStream_t s) {
   switch (dc) {
-    case 64: return ncc_jobs_rdc<r, T, 64>(quad, jobs, first, n, blocks, s);
-    case 32: return ncc_jobs_rdc<r, T, 32>(quad, jobs, first, n, blocks, s);
-    default: return ncc_jobs_rdc<r, T, 16>(quad, jobs, first, n, blocks, s);
+    case 64: return ncc_jobs_rdc<r, T, 64>(quad, jobs, first, n, blocks, base, s);
+    case 32: return ncc_jobs_rdc<r, T, 32>(quad, jobs, first, n, blocks, base, s);
+    default: return ncc_jobs_rdc<r, T, 16>(quad, jobs, first, n, blocks, base, s);
   }
 }
 
