@@ -274,10 +274,8 @@ stereo_status stereo_cost_volume(stereo_plan_t plan, const void* ref, const floa
   stereo_status s = check_ws(P, ws, ws_bytes);
   if (s != STEREO_OK) return s;
   StatMaps m = stat_maps(P, ws);
-  STEREO_HIP(launch_block_stats(P, ref, P.p.dtype, P.p.pitch_ref, m.zX, m.isdX, stream),
-             "block statistics (ref)");
-  STEREO_HIP(launch_block_stats(P, tar_w, STEREO_F32, P.W, m.zY, m.isdY, stream),
-             "block statistics (tar_w)");
+  STEREO_HIP(launch_block_stats2(P, ref, P.p.dtype, P.p.pitch_ref, tar_w, m.zX, m.isdX, m.zY,
+                                 m.isdY, stream), "block statistics");
   const int64_t slice = (int64_t)P.W * P.H;
   STEREO_HIP(launch_ncc(P, ref, tar_w, m.zX, m.isdX, m.zY, m.isdY, cost_R, P.W, P.W, slice,
                         0, stream), "ncc (reference volume)");
@@ -361,10 +359,8 @@ stereo_status match_impl(stereo_plan_t plan, const void* ref, const void* tar,
   STEREO_HIP(st ? launch_warp_tracked(P, tar, st, tarw, stream)
                 : launch_warp(P, tar, tarw, stream), "warp");
   STEREO_HIP(mark(1), "event record");
-  STEREO_HIP(launch_block_stats(P, ref, P.p.dtype, P.p.pitch_ref, m.zX, m.isdX, stream),
-             "block statistics (ref)");
-  STEREO_HIP(launch_block_stats(P, tarw, STEREO_F32, P.W, m.zY, m.isdY, stream),
-             "block statistics (tar_w)");
+  STEREO_HIP(launch_block_stats2(P, ref, P.p.dtype, P.p.pitch_ref, tarw, m.zX, m.isdX, m.zY,
+                                 m.isdY, stream), "block statistics");
   STEREO_HIP(mark(2), "event record");
   const bool lr = P.p.lr_check != 0;
   BilArgs a{};

@@ -85,6 +85,10 @@ hipError_t launch_warp_tracked(const Plan& P, const void* tar, const stereo_plan
 // z = mu / sigma and isd = 1 / sigma of (I - 128) over the clamped (2r+1)^2
 // block centred at every column x in [-r, W + r) and row y; a flat block
 // stores z = isd = 0.
+// Statistics of the reference (dt) and the warped target (FP32) in one launch.
+hipError_t launch_block_stats2(const Plan& P, const void* ref, stereo_dtype dt,
+                               int64_t ref_pitch, const float* tarw, float* zX, float* isdX,
+                               float* zY, float* isdY, hipStream_t s);
 hipError_t launch_block_stats(const Plan& P, const void* img, stereo_dtype dt,
                               int64_t pitch, float* z, float* isd,
                               hipStream_t s);

@@ -120,11 +120,22 @@ __device__ __forceinline__ void block_stats_body(const T* __restrict__ img, int6
   const int tw = ST_TX + 2 * r, th = ST_TY + 2 * r;
   const int xc0 = bx * ST_TX - r;            // first block centre (image col)
   const int y0 = by * ST_TY;
-  for (int i = threadIdx.x; i < tw * th; i += blockDim.x) {
-    const int yy = i / tw, xx = i - yy * tw;
-    const int gy = min(max(y0 - r + yy, 0), H - 1);
-    const int gx = min(max(xc0 - r + xx, 0), W - 1);
-    tile[i] = ld(img + (int64_t)gy * pitch + gx) - kOffset;
+  // staged in chunks: four loads of a thread in flight before their stores
+  for (int i0 = threadIdx.x; i0 < tw * th; i0 += 4 * (int)blockDim.x) {
+    float v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = min(i0 + k * (int)blockDim.x, tw * th - 1);
+      const int yy = i / tw, xx = i - yy * tw;
+      const int gy = min(max(y0 - r + yy, 0), H - 1);
+      const int gx = min(max(xc0 - r + xx, 0), W - 1);
+      v[k] = ld(img + (int64_t)gy * pitch + gx);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + k * (int)blockDim.x;
+      if (i < tw * th) tile[i] = v[k] - kOffset;
+    }
   }
   // column sums of the block rows of each output row: [ST_TY][tw], x and x^2
   double* cs = reinterpret_cast<double*>(tile + tw * th);
@@ -168,6 +179,20 @@ block_stats_kernel(const T* __restrict__ img, int64_t pitch, int W, int H, int r
                    float* __restrict__ zmap, float* __restrict__ isd) {
   extern __shared__ float tile[];   // (ST_TY + 2r) x (ST_TX + 2r)
   block_stats_body<T>(img, pitch, W, H, r, zmap, isd, tile, blockIdx.x, blockIdx.y);
+}
+
+// Both images of a pair in one launch: blockIdx.z = 0 the reference (T),
+// 1 the warped target (FP32).
+template <typename T>
+__global__ void __launch_bounds__(256)
+block_stats2_kernel(const T* __restrict__ ref, int64_t ref_pitch, const float* __restrict__ tarw,
+                    int W, int H, int r, float* __restrict__ zX, float* __restrict__ isdX,
+                    float* __restrict__ zY, float* __restrict__ isdY) {
+  extern __shared__ float tile[];
+  if (blockIdx.z == 0)
+    block_stats_body<T>(ref, ref_pitch, W, H, r, zX, isdX, tile, blockIdx.x, blockIdx.y);
+  else
+    block_stats_body<float>(tarw, W, W, H, r, zY, isdY, tile, blockIdx.x, blockIdx.y);
 }
 
 template <typename T>
@@ -337,6 +362,21 @@ hipError_t launch_warp_tracked(const Plan& P, const void* tar, const stereo_plan
   else
     hipLaunchKernelGGL(warp_tracked_kernel<float>, grid, dim3(256), 0, s,
                        (const float*)tar, P.p.pitch_tar, P.W, dp, st, tar_w);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_stats2(const Plan& P, const void* ref, stereo_dtype dt,
+                               int64_t ref_pitch, const float* tarw, float* zX, float* isdX,
+                               float* zY, float* isdY, hipStream_t s) {
+  const int SW = P.W + 2 * P.r;
+  dim3 grid((SW + ST_TX - 1) / ST_TX, (P.H + ST_TY - 1) / ST_TY, 2);
+  const size_t lds = stats_lds_bytes(P.r);
+  if (dt == STEREO_U8)
+    hipLaunchKernelGGL(block_stats2_kernel<uint8_t>, grid, dim3(256), lds, s,
+                       (const uint8_t*)ref, ref_pitch, tarw, P.W, P.H, P.r, zX, isdX, zY, isdY);
+  else
+    hipLaunchKernelGGL(block_stats2_kernel<float>, grid, dim3(256), lds, s, (const float*)ref,
+                       ref_pitch, tarw, P.W, P.H, P.r, zX, isdX, zY, isdY);
   return hipGetLastError();
 }
 

@@ -899,8 +899,8 @@ stereo_status stereo_soft_forward(stereo_plan_t plan, const float* ref, const fl
   Maps m = maps_of(P, ws);
   float* cvol = at<float>(ws, P.off_cvol);
   HIPC(launch_warp(P, tar, tarw, stream), "warp");
-  HIPC(launch_block_stats(P, ref, STEREO_F32, P.p.pitch_ref, m.zX, m.isdX, stream), "stats");
-  HIPC(launch_block_stats(P, tarw, STEREO_F32, P.W, m.zY, m.isdY, stream), "stats");
+  HIPC(launch_block_stats2(P, ref, STEREO_F32, P.p.pitch_ref, tarw, m.zX, m.isdX, m.zY, m.isdY,
+                           stream), "stats");
   BilArgs a{};
   if (P.agg_engine == 2) {
     // split-FP16 reference-anchored volume for the FP16-operand matrix cores
@@ -1007,8 +1007,8 @@ stereo_status stereo_backward_profiled(stereo_plan_t plan, const float* ref, con
 
   // forward state that is cheap to rebuild: warp, block statistics
   HIPC(launch_warp(P, tar, tarw, stream), "warp");
-  HIPC(launch_block_stats(P, ref, STEREO_F32, P.p.pitch_ref, m.zX, m.isdX, stream), "stats");
-  HIPC(launch_block_stats(P, tarw, STEREO_F32, W, m.zY, m.isdY, stream), "stats");
+  HIPC(launch_block_stats2(P, ref, STEREO_F32, P.p.pitch_ref, tarw, m.zX, m.isdX, m.zY, m.isdY,
+                           stream), "stats");
   float* muX = R_(GR_MU);
   float* muY = muX + (int64_t)H * (W + 2 * r);
   {
