@@ -204,29 +204,53 @@ __device__ __forceinline__ void stage(const View& v, int x0, int y0, int d0, flo
   }
 }
 
-// Guide of the tile's halo, scaled by sqrt(kr2), into registers (kFar outside).
+// Guide of a tile's halo: the raw values are loaded into registers
+// (unconditionally, clamped addresses) and turned into the scaled guide
+// (sqrt(kr2) g, kFar outside the image) only when stored to LDS.  A value
+// used right after its load waits at once, and that wait also covers the
+// slab copies in flight; this way the loads of the next tile's guide overlap
+// the last pass's products.
 template <int R, typename GT>
-__device__ __forceinline__ void guide_load(const View& v, int x0, int y0, float (&g)[HGeom<R>::GPT]) {
+struct GuideRaw {
+  GT raw[HGeom<R>::GPT];
+};
+
+template <int R, typename GT>
+__device__ __forceinline__ void guide_load(const View& v, int x0, int y0, GuideRaw<R, GT>& g) {
   using G = HGeom<R>;
   const GT* __restrict__ src = static_cast<const GT*>(v.guide);
+#pragma unroll
+  for (int k = 0; k < G::GPT; ++k) {
+    const int i = threadIdx.x + k * kThreads;
+    const int yy = i / G::GS, xx = i % G::GS;
+    const int cy = min(max(y0 - R + yy, 0), v.H - 1), cx = min(max(x0 - R + xx, 0), v.W - 1);
+    g.raw[k] = src[(int64_t)cy * v.g_pitch + cx];
+  }
+}
+
+__device__ __forceinline__ float guide_value(uint8_t raw, unsigned z) {
+  return (float)((unsigned)raw ^ z);
+}
+__device__ __forceinline__ float guide_value(float raw, unsigned z) {
+  return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, raw) ^ z);
+}
+
+// (v, x0, y0): the tile the guide was loaded for
+template <int R, typename GT>
+__device__ __forceinline__ void guide_store(float* gs, const GuideRaw<R, GT>& g, const View& v,
+                                            int x0, int y0) {
+  using G = HGeom<R>;
+  // an opaque zero: the conversion cannot move up into the load's branch
+  unsigned z = 0u;
+  asm volatile("" : "+s"(z));
   const float kr = sqrtf(v.kr2);
 #pragma unroll
   for (int k = 0; k < G::GPT; ++k) {
     const int i = threadIdx.x + k * kThreads;
     const int yy = i / G::GS, xx = i % G::GS;
     const int gy = y0 - R + yy, gx = x0 - R + xx;
-    const bool in = i < G::GUIDE && xx < kTW + 2 * R && gy >= 0 && gy < v.H && gx >= 0 && gx < v.W;
-    g[k] = in ? (float)src[(int64_t)gy * v.g_pitch + gx] * kr : kFar;
-  }
-}
-
-template <int R>
-__device__ __forceinline__ void guide_store(float* gs, const float (&g)[HGeom<R>::GPT]) {
-  using G = HGeom<R>;
-#pragma unroll
-  for (int k = 0; k < G::GPT; ++k) {
-    const int i = threadIdx.x + k * kThreads;
-    if (i < G::GUIDE) gs[i] = g[k];
+    const bool in = xx < kTW + 2 * R && gy >= 0 && gy < v.H && gx >= 0 && gx < v.W;
+    if (i < G::GUIDE) gs[i] = in ? guide_value(g.raw[k], z) * kr : kFar;
   }
 }
 
@@ -399,10 +423,10 @@ agg_mfma16_kernel(View one, const BilPair* __restrict__ pairs, const int* __rest
     View cv;
     int cx0, cy0;
     resolve(cur, cv, cx0, cy0);
-    float g[G::GPT];
+    GuideRaw<R, GT> g;
     stage<R>(cv, cx0, cy0, 0, buf0, wave, lane, coff, !QUEUE || G::CPR == 64);
     guide_load<R, GT>(cv, cx0, cy0, g);
-    guide_store<R>(gbuf0, g);
+    guide_store<R, GT>(gbuf0, g, cv, cx0, cy0);
   }
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
@@ -501,11 +525,14 @@ agg_mfma16_kernel(View one, const BilPair* __restrict__ pairs, const int* __rest
       passes = (D + 15) / 16;
     }
     for (int p = 0; p < passes; ++p) {
+      // the pass reads one buffer while the copies fill the other; as
+      // __restrict__ parameters the compiler knows that they do not alias
+      // and does not wait for the copies before the pass's first LDS read
+      // (1280x720, D = 64, R = 7: 0.272 -> 0.257 ms per launch)
+      auto pass_body = [&](float* __restrict__ cbuf, float* __restrict__ obuf) {
       const int d0 = 16 * p;
-      float* cbuf = par ? buf1 : buf0;
-      float* obuf = par ? buf0 : buf1;
       const bool last = p + 1 == passes;
-      float gq[G::GPT];
+      GuideRaw<R, GT> gq;
       if (!last || has_next) {
         View sv;
         int sx0, sy0;
@@ -610,9 +637,16 @@ agg_mfma16_kernel(View one, const BilPair* __restrict__ pairs, const int* __rest
         }
         mr = M;
       }
-      if (last && has_next) guide_store<R>(gpar ? gbuf0 : gbuf1, gq);
+      if (last && has_next) {
+        View gv = nv;
+        int gx0 = nx0, gy0 = ny0;
+        if (!QUEUE) resolve(nxt, gv, gx0, gy0);
+        guide_store<R, GT>(gpar ? gbuf0 : gbuf1, gq, gv, gx0, gy0);
+      }
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
+      };
+      pass_body(par ? buf1 : buf0, par ? buf0 : buf1);
       par ^= 1;
     }
     if constexpr (MODE == 2) {

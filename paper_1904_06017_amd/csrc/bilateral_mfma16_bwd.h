@@ -182,10 +182,10 @@ __global__ void __launch_bounds__(kThreads, 1) agg_mfma16_bwd_kernel(BView b) {
   {
     int cx0, cy0;
     origin(cur, cx0, cy0);
-    float g[G::GPT];
+    GuideRaw<R, float> g;
     stage<R>(one, cx0, cy0, 0, buf0, wave, lane, coff, true);
     guide_load<R, float>(one, cx0, cy0, g);
-    guide_store<R>(gbuf0, g);
+    guide_store<R, float>(gbuf0, g, one, cx0, cy0);
   }
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
@@ -315,12 +315,13 @@ __global__ void __launch_bounds__(kThreads, 1) agg_mfma16_bwd_kernel(BView b) {
       }
     };
     for (int p = 0; p < passes; ++p) {
+      // the two slab buffers as __restrict__ parameters: the products need
+      // not wait for the copies into the other buffer
+      auto pass_body = [&](float* __restrict__ cbuf, float* __restrict__ obuf) {
       const int d0 = 16 * p;
-      float* cbuf = par ? buf1 : buf0;
-      float* obuf = par ? buf0 : buf1;
       const bool last = p + 1 == passes;
       flush();
-      float gq[G::GPT];
+      GuideRaw<R, float> gq;
       if (!last || has_next) {
         stage<R>(one, last ? nx0 : x0, last ? ny0 : y0, last ? 0 : d0 + 16, obuf, wave, lane,
                  coff, true);
@@ -450,9 +451,11 @@ __global__ void __launch_bounds__(kThreads, 1) agg_mfma16_bwd_kernel(BView b) {
           sums[16 + so + v] += cb2[v];
         }
       }
-      if (last && has_next) guide_store<R>(gpar ? gbuf0 : gbuf1, gq);
+      if (last && has_next) guide_store<R, float>(gpar ? gbuf0 : gbuf1, gq, one, nx0, ny0);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
+      };
+      pass_body(par ? buf1 : buf0, par ? buf0 : buf1);
       par ^= 1;
       ++gpass;
     }
