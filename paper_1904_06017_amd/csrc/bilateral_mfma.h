@@ -373,9 +373,10 @@ agg_wta_mfma_kernel(View one, const BilPair* __restrict__ pairs, const int* __re
       passes = (D + 15) / 16;
     }
     for (int p = 0; p < passes; ++p) {
+      // the two slab buffers as __restrict__ parameters: the products need
+      // not wait for the copies into the other buffer
+      auto pass_body = [&](float* __restrict__ cbuf, float* __restrict__ obuf) {
       const int d0 = 16 * p;
-      float* cbuf = par ? buf1 : buf0;
-      float* obuf = par ? buf0 : buf1;
       const bool last = p + 1 == passes;
       float gq[G::GPT];
       int shift;
@@ -478,6 +479,8 @@ agg_wta_mfma_kernel(View one, const BilPair* __restrict__ pairs, const int* __re
       if (last && has_next) guide_store<R>(gpar ? gbuf0 : gbuf1, gq);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
+      };
+      pass_body(par ? buf1 : buf0, par ? buf0 : buf1);
       par ^= 1;
     }
     if constexpr (MODE == 2) {
