@@ -334,7 +334,7 @@ def batched(args, scenes):
                 per_pair_gpd_s=round(el / (t_p / 1e3) / 1e9, 3),
                 speedup_vs_per_pair=round(t_p / t_b, 3), equal_to_per_pair=bool(same),
                 tuning={k: b.get_tuning(k) for k in ("agg_engine", "tile_band", "ncc_levels",
-                                                     "wg_per_cu", "agg_levels_u8",
+                                                     "group_overlap", "wg_per_cu", "agg_levels_u8",
                                                      "agg_levels_f32")},
                 autotune_best_ms=round(tuned_ms, 3), roofline=roof)
 

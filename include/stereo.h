@@ -321,8 +321,11 @@ stereo_status stereo_batch_workspace_bytes(stereo_batch_t b, size_t* bytes);
  * in bands of this many 16-pixel tile columns, row by row; 1, 2, 4, 8, 16
  * or 32, default 4; changes only the order of independent tiles, never the
  * results), "ncc_levels" (levels per workgroup of the batch's NCC launches:
- * 0 = automatic, default, or 16, 32, 64; never changes the results).  Drops
- * an instantiated graph. */
+ * 0 = automatic, default, or 16, 32, 64; never changes the results),
+ * "group_overlap" (split-FP16 engine: 1, default, runs the aggregation of
+ * the radii below the largest on a second stream, a graph branch when
+ * captured, beside the NCC of the largest radius; 0 runs every stage in
+ * order; never changes the results).  Drops an instantiated graph. */
 stereo_status stereo_batch_set_tuning(stereo_batch_t b, const char* key, int32_t value);
 stereo_status stereo_batch_get_tuning(stereo_batch_t b, const char* key, int32_t* value);
 /* Enqueue the whole batch on `stream` (no graph).  The first call with a given
@@ -349,7 +352,8 @@ stereo_status stereo_batch_destroy(stereo_batch_t b);
  * Plans: "ncc_levels" (16, 32, 64), and with agg_engine = 0 also
  * "agg_levels_u8" / "agg_levels_f32"; batches: with agg_engine = 0
  * "wg_per_cu" and the levels per pass, with the matrix-core engines
- * "tile_band" (2, 4, 8, 16) and "ncc_levels" (16, 32, 64).  best_ms (nullable) receives
+ * "tile_band" (2, 4, 8, 16), "ncc_levels" (16, 32, 64) and, with the
+ * split-FP16 engine, "group_overlap" (0, 1).  best_ms (nullable) receives
  * the time of the chosen variant.  Results never depend on the variant.
  * stereo_plan_autotune allocates temporary outputs (hipMalloc). */
 stereo_status stereo_plan_autotune(stereo_plan_t plan, const void* ref, const void* tar,

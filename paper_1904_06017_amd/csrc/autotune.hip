@@ -220,9 +220,9 @@ stereo_status stereo_batch_autotune(stereo_batch_t b, void* ws, size_t ws_bytes,
   // key: architecture + FNV-1a hash of every pair's shape
   uint64_t h = 1469598103934665603ull;
   int32_t n = 0;
-  constexpr int NK = 5;
+  constexpr int NK = 6;
   const char* keys[NK] = {"wg_per_cu", "agg_levels_u8", "agg_levels_f32", "tile_band",
-                          "ncc_levels"};
+                          "ncc_levels", "group_overlap"};
   int32_t cur[NK];
   for (int k = 0; k < NK; ++k) stereo_batch_get_tuning(b, keys[k], &cur[k]);
   // shapes are hashed through the workspace size and the plan shapes
@@ -256,9 +256,11 @@ stereo_status stereo_batch_autotune(stereo_batch_t b, void* ws, size_t ws_bytes,
   // the vector-ALU engine's knobs are its workgroups per CU and levels per
   // pass; the matrix-core engines' are the band width of their tile list (the
   // 2-D patch of tiles an XCD works on at a time: L2 reuse of the halos) and
-  // the NCC level block of the batch's job lists
+  // the NCC level block of the batch's job lists, and with the split-FP16
+  // engine whether the smaller radii's aggregation overlaps the largest
+  // radius's NCC
   double best = 1e30;
-  int32_t bestv[NK] = {cur[0], cur[1], cur[2], cur[3], cur[4]};
+  int32_t bestv[NK] = {cur[0], cur[1], cur[2], cur[3], cur[4], cur[5]};
   stereo_status st = STEREO_OK;
   const std::vector<int> wgs = engine == 0 ? std::vector<int>{1, 2, 3, 4} : std::vector<int>{cur[0]};
   const std::vector<int> lvls = engine == 0 ? std::vector<int>{8, 16} : std::vector<int>{cur[1]};
@@ -266,8 +268,11 @@ stereo_status stereo_batch_autotune(stereo_batch_t b, void* ws, size_t ws_bytes,
                                              : std::vector<int>{2, 4, 8, 16};
   const std::vector<int> nccs = engine == 0 ? std::vector<int>{cur[4]}
                                             : std::vector<int>{16, 32, 64};
-  for (size_t v = 0; v < wgs.size() * lvls.size() * bands.size() * nccs.size(); ++v) {
+  const std::vector<int> ovs = engine == 2 ? std::vector<int>{0, 1} : std::vector<int>{cur[5]};
+  for (size_t v = 0; v < wgs.size() * lvls.size() * bands.size() * nccs.size() * ovs.size();
+       ++v) {
     size_t q = v;
+    const int ov = ovs[q % ovs.size()]; q /= ovs.size();
     const int nv = nccs[q % nccs.size()]; q /= nccs.size();
     const int bd = bands[q % bands.size()]; q /= bands.size();
     const int lv = lvls[q % lvls.size()]; q /= lvls.size();
@@ -277,20 +282,22 @@ stereo_status stereo_batch_autotune(stereo_batch_t b, void* ws, size_t ws_bytes,
     stereo_batch_set_tuning(b, "agg_levels_f32", lv);
     stereo_batch_set_tuning(b, "tile_band", bd);
     stereo_batch_set_tuning(b, "ncc_levels", nv);
+    stereo_batch_set_tuning(b, "group_overlap", ov);
     double ms = 0.0;
     st = time_ms(stream, reps,
                  [&]() { return stereo_submit_batch(b, ws, ws_bytes, stream); }, &ms);
     if (st != STEREO_OK) break;
     if (ms < best) {
       best = ms;
-      bestv[0] = wg; bestv[1] = lv; bestv[2] = lv; bestv[3] = bd; bestv[4] = nv;
+      bestv[0] = wg; bestv[1] = lv; bestv[2] = lv; bestv[3] = bd; bestv[4] = nv; bestv[5] = ov;
     }
   }
   for (int k = 0; k < NK; ++k) stereo_batch_set_tuning(b, keys[k], bestv[k]);
   if (st != STEREO_OK) return st;
   cache[key] = Entry{{"wg_per_cu", (double)bestv[0]}, {"agg_levels_u8", (double)bestv[1]},
                      {"agg_levels_f32", (double)bestv[2]}, {"tile_band", (double)bestv[3]},
-                     {"ncc_levels", (double)bestv[4]}, {"ms", best}};
+                     {"ncc_levels", (double)bestv[4]}, {"group_overlap", (double)bestv[5]},
+                     {"ms", best}};
   save_cache(cache_path, cache);
   if (best_ms) *best_ms = best;
   return STEREO_OK;

@@ -65,6 +65,8 @@ struct stereo_batch_s {
   int wg_per_cu = 2;
   int tile_band = 4;                   // tile columns per band of the matrix-core tile list
   int ncc_levels = 0;                  // NCC levels per workgroup (0: automatic)
+  int overlap = 1;                     // split-FP16 engine: the aggregation of the
+                                       // smaller radii beside the largest radius's NCC
   int levels_u8 = 8, levels_f32 = 8;
   int engine = 2;                      // aggregation engine: 2 / 1 matrix cores with split-FP16
                                        // / FP32 operands, 0 vector ALU
@@ -72,6 +74,8 @@ struct stereo_batch_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t capture = nullptr;
+  hipStream_t side = nullptr;          // second branch of the overlapped schedule
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace {
@@ -341,6 +345,21 @@ stereo_status bind(stereo_batch_s& b, void* ws, size_t bytes, hipStream_t s) {
 stereo_status enqueue(stereo_batch_s& b, hipStream_t s, hipEvent_t* ev = nullptr) {
   void* ws = b.bound_ws;
   BREQ(ws, "batch not bound to a workspace");
+  // the split-FP16 NCC of pair i (both anchored volumes), one launch
+  auto ncc_pair = [&](int i) -> stereo_status {
+    Plan P = b.plans[i];
+    if (b.ncc_levels) P.ncc_levels = b.ncc_levels;
+    void* pws = at<char>(ws, b.pair_ws[i]);
+    const float* tarw = at<float>(pws, P.off_tarw);
+    const float* st = at<float>(pws, P.off_stats);
+    const size_t sn = (size_t)P.stats_w * P.H;
+    BHIP(launch_ncc(P, b.items[i].ref, tarw, st, st + sn, st + 2 * sn, st + 3 * sn,
+                    at<float>(pws, P.off_cvol), ncc_both_extent(P.h2_pitch, 0, P.D), P.h2_pitch,
+                    16 * (int64_t)P.H * P.h2_pitch, 0, s, 0, -1, 4, P.R,
+                    P.p.lr_check ? at<float>(pws, P.off_cvol + P.h2_tar_off) : nullptr),
+         "batch ncc (per pair)");
+    return STEREO_OK;
+  };
   auto run_list = [&](const JobList& L) -> stereo_status {
     const int nj = (int)L.pair.size();
     const int blocks = L.first.back();
@@ -365,18 +384,8 @@ stereo_status enqueue(stereo_batch_s& b, hipStream_t s, hipEvent_t* ev = nullptr
           // against 8.9 ms)
           for (size_t k = 0; k < L.pair.size(); ++k) {
             if (L.which[k] != 0) continue;
-            const int i = L.pair[k];
-            Plan P = b.plans[i];
-            if (b.ncc_levels) P.ncc_levels = b.ncc_levels;
-            void* pws = at<char>(ws, b.pair_ws[i]);
-            const float* tarw = at<float>(pws, P.off_tarw);
-            const float* st = at<float>(pws, P.off_stats);
-            const size_t sn = (size_t)P.stats_w * P.H;
-            BHIP(launch_ncc(P, b.items[i].ref, tarw, st, st + sn, st + 2 * sn, st + 3 * sn,
-                            at<float>(pws, P.off_cvol), ncc_both_extent(P.h2_pitch, 0, P.D),
-                            P.h2_pitch, 16 * (int64_t)P.H * P.h2_pitch, 0, s, 0, -1, 4, P.R,
-                            P.p.lr_check ? at<float>(pws, P.off_cvol + P.h2_tar_off) : nullptr),
-                 "batch ncc (per pair)");
+            stereo_status st = ncc_pair(L.pair[k]);
+            if (st != STEREO_OK) return st;
           }
           break;
         }
@@ -392,39 +401,98 @@ stereo_status enqueue(stereo_batch_s& b, hipStream_t s, hipEvent_t* ev = nullptr
     return STEREO_OK;
   };
   // warp first (the target statistics read its output), then statistics, NCC
-  for (JobKind k : {JK_WARP, JK_STATS, JK_NCC})
-    for (const JobList& L : b.lists)
-      if (L.kind == k) {
-        stereo_status st = run_list(L);
-        if (st != STEREO_OK) return st;
-      }
   unsigned int* ctr = at<unsigned int>(ws, b.counter_off);
   const int ng = (int)b.groups.size();
-  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, ctr, ng);
-  BHIP(hipGetLastError(), "zero counters");
   const void* desc = at<char>(ws, b.desc_off);
-  if (ev) BHIP(hipEventRecord(ev[0], s), "event record");
-  for (int g = 0; g < ng; ++g) {
+  auto run_group = [&](int g, hipStream_t st) -> stereo_status {
     const Group& G = b.groups[g];
     if (b.engine >= 1) {                 // one workgroup per CU holds the whole LDS
       const int nt = (int)G.tiles_m.size() / 3;
       const int groups = std::max(1, std::min(nt, b.cu_count));
       BHIP(launch_bilateral_persistent(b.engine, G.R, G.gdt, G.levels, desc,
-                                       at<int>(ws, G.tiles_m_off), nt, ctr + g, groups, s),
+                                       at<int>(ws, G.tiles_m_off), nt, ctr + g, groups, st),
            "batch aggregation");
     } else {
       const int nt = (int)G.tiles.size() / 3;
       const int groups = std::max(1, std::min(nt, b.cu_count * b.wg_per_cu));
       BHIP(launch_bilateral_persistent(0, G.R, G.gdt, G.levels, desc, at<int>(ws, G.tiles_off), nt,
-                                       ctr + g, groups, s), "batch aggregation");
+                                       ctr + g, groups, st), "batch aggregation");
     }
+    return STEREO_OK;
+  };
+  int rmax = 0, rmin = 1 << 30;
+  for (const Group& G : b.groups) {
+    rmax = std::max(rmax, G.R);
+    rmin = std::min(rmin, G.R);
   }
-  if (ev) BHIP(hipEventRecord(ev[1], s), "event record");
+  if (b.engine == 2 && b.overlap && !ev && b.side && rmin < rmax) {
+    // overlapped schedule: the NCC of the pairs below the largest radius
+    // first; their aggregation groups then run on a second branch (graph
+    // branch when captured) while the main one computes the NCC of the
+    // largest radius and aggregates it; the LR check joins both
+    for (JobKind k : {JK_WARP, JK_STATS})
+      for (const JobList& L : b.lists)
+        if (L.kind == k) {
+          stereo_status st = run_list(L);
+          if (st != STEREO_OK) return st;
+        }
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, ctr, ng);
+    BHIP(hipGetLastError(), "zero counters");
+    auto ncc_pairs = [&](bool small) -> stereo_status {
+      for (const JobList& L : b.lists) {
+        if (L.kind != JK_NCC) continue;
+        for (size_t k = 0; k < L.pair.size(); ++k) {
+          if (L.which[k] != 0) continue;
+          const int i = L.pair[k];
+          if ((b.plans[i].R < rmax) != small) continue;
+          stereo_status st = ncc_pair(i);
+          if (st != STEREO_OK) return st;
+        }
+      }
+      return STEREO_OK;
+    };
+    stereo_status st = ncc_pairs(true);
+    if (st != STEREO_OK) return st;
+    BHIP(hipEventRecord(b.fork, s), "event record");
+    BHIP(hipStreamWaitEvent(b.side, b.fork, 0), "stream wait");
+    for (int g = 0; g < ng; ++g)
+      if (b.groups[g].R < rmax && (st = run_group(g, b.side)) != STEREO_OK) return st;
+    BHIP(hipEventRecord(b.join, b.side), "event record");
+    if ((st = ncc_pairs(false)) != STEREO_OK) return st;
+    for (int g = 0; g < ng; ++g)
+      if (b.groups[g].R == rmax && (st = run_group(g, s)) != STEREO_OK) return st;
+    BHIP(hipStreamWaitEvent(s, b.join, 0), "stream wait");
+  } else {
+    for (JobKind k : {JK_WARP, JK_STATS, JK_NCC})
+      for (const JobList& L : b.lists)
+        if (L.kind == k) {
+          stereo_status st = run_list(L);
+          if (st != STEREO_OK) return st;
+        }
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, ctr, ng);
+    BHIP(hipGetLastError(), "zero counters");
+    if (ev) BHIP(hipEventRecord(ev[0], s), "event record");
+    for (int g = 0; g < ng; ++g) {
+      stereo_status st = run_group(g, s);
+      if (st != STEREO_OK) return st;
+    }
+    if (ev) BHIP(hipEventRecord(ev[1], s), "event record");
+  }
   for (const JobList& L : b.lists)
     if (L.kind == JK_LR) {
       stereo_status st = run_list(L);
       if (st != STEREO_OK) return st;
     }
+  return STEREO_OK;
+}
+
+// The second stream and the two events of the overlapped schedule (created
+// outside any capture; default priority).
+stereo_status ensure_side(stereo_batch_s& b) {
+  if (b.engine != 2 || !b.overlap) return STEREO_OK;
+  if (!b.side) BHIP(hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking), "stream");
+  if (!b.fork) BHIP(hipEventCreateWithFlags(&b.fork, hipEventDisableTiming), "event");
+  if (!b.join) BHIP(hipEventCreateWithFlags(&b.join, hipEventDisableTiming), "event");
   return STEREO_OK;
 }
 
@@ -500,6 +568,9 @@ stereo_status stereo_batch_set_tuning(stereo_batch_t b, const char* key, int32_t
       ncc_blocks(*b);                   // block counts of the NCC job lists
       b->bound_ws = nullptr;            // tables are uploaded again
     }
+  } else if (k == "group_overlap") {
+    BREQ(value == 0 || value == 1, "group_overlap must be 0 or 1");
+    b->overlap = value;
   } else if (k == "agg_engine") {
     BREQ(value >= 0 && value <= 2,
          "agg_engine must be 0 (vector ALU), 1 (matrix cores, FP32 operands) or 2 (matrix "
@@ -519,6 +590,7 @@ stereo_status stereo_batch_get_tuning(stereo_batch_t b, const char* key, int32_t
   if (k == "wg_per_cu") *value = b->wg_per_cu;
   else if (k == "tile_band") *value = b->tile_band;
   else if (k == "ncc_levels") *value = b->ncc_levels;
+  else if (k == "group_overlap") *value = b->overlap;
   else if (k == "agg_levels_u8") *value = b->levels_u8;
   else if (k == "agg_levels_f32") *value = b->levels_f32;
   else if (k == "agg_engine") *value = b->engine;
@@ -542,6 +614,7 @@ stereo_status stereo_submit_batch_profiled(stereo_batch_t b, void* ws, size_t ws
   }
   stereo_status s = bind(*b, ws, ws_bytes, stream);
   if (s != STEREO_OK) return s;
+  if ((s = ensure_side(*b)) != STEREO_OK) return s;
   return enqueue(*b, stream, ev);
 }
 
@@ -557,6 +630,7 @@ stereo_status stereo_batch_instantiate(stereo_batch_t b, void* ws, size_t ws_byt
   stereo_status s = bind(*b, ws, ws_bytes, stream);
   if (s != STEREO_OK) return s;
   drop_graph(*b);
+  if ((s = ensure_side(*b)) != STEREO_OK) return s;
   if (!b->capture) BHIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "stream");
   BHIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "begin capture");
   s = enqueue(*b, b->capture);
@@ -582,6 +656,9 @@ stereo_status stereo_batch_destroy(stereo_batch_t b) {
   if (!b) return STEREO_OK;
   drop_graph(*b);
   if (b->capture) hipStreamDestroy(b->capture);
+  if (b->side) hipStreamDestroy(b->side);
+  if (b->fork) hipEventDestroy(b->fork);
+  if (b->join) hipEventDestroy(b->join);
   delete b;
   return STEREO_OK;
 }

@@ -146,6 +146,10 @@ def test_batch_tuning_keys(lib):
         assert lib.stereo_batch_get_tuning(b, b"ncc_levels", ctypes.byref(v)) == 0
         assert v.value == nl
     assert lib.stereo_batch_set_tuning(b, b"ncc_levels", 48) == 1
+    assert lib.stereo_batch_get_tuning(b, b"group_overlap", ctypes.byref(v)) == 0 and v.value == 1
+    assert lib.stereo_batch_set_tuning(b, b"group_overlap", 0) == 0
+    assert lib.stereo_batch_get_tuning(b, b"group_overlap", ctypes.byref(v)) == 0 and v.value == 0
+    assert lib.stereo_batch_set_tuning(b, b"group_overlap", 2) == 1
     assert lib.stereo_batch_get_tuning(b, b"tile_band", ctypes.byref(v)) == 0 and v.value == 4
     assert lib.stereo_batch_set_tuning(b, b"tile_band", 3) == 1
     assert lib.stereo_batch_set_tuning(b, b"no_such_key", 8) == 1

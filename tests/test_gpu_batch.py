@@ -117,18 +117,20 @@ def test_batch_tuning_does_not_change_results(small_batch):
     items = _make(small_batch)
     b = api.Batch(items)
     ref = [{k: _host(v) for k, v in o.items()} for o in b.submit()]
-    for wg, lv, band, nl in ((1, 16, 1, 16), (4, 8, 32, 64), (2, 8, 2, 32)):
+    for wg, lv, band, nl, ov in ((1, 16, 1, 16, 0), (4, 8, 32, 64, 1), (2, 8, 2, 32, 0)):
         b.set_tuning("wg_per_cu", wg)
         b.set_tuning("agg_levels_u8", lv)
         b.set_tuning("agg_levels_f32", lv)
         b.set_tuning("tile_band", band)      # the matrix-core engine's tile order
         b.set_tuning("ncc_levels", nl)       # the NCC level block of the job lists
+        b.set_tuning("group_overlap", ov)    # the two-branch schedule
         assert b.get_tuning("tile_band") == band
         assert b.get_tuning("ncc_levels") == nl
+        assert b.get_tuning("group_overlap") == ov
         got = [{k: _host(v) for k, v in o.items()} for o in b.submit()]
         for e, g in zip(ref, got):
             for k in e:
-                assert np.array_equal(e[k], g[k], equal_nan=True), (wg, lv, band, nl, k)
+                assert np.array_equal(e[k], g[k], equal_nan=True), (wg, lv, band, nl, ov, k)
 
 
 def test_batch_pairs_match_the_oracle(small_batch):
@@ -181,6 +183,8 @@ def test_batch_autotune(small_batch, tmp_path):
     assert b.get_tuning("tile_band") == int(entries[key]["tile_band"])
     assert int(entries[key]["ncc_levels"]) in (16, 32, 64)
     assert b.get_tuning("ncc_levels") == int(entries[key]["ncc_levels"])
+    assert int(entries[key]["group_overlap"]) in (0, 1)
+    assert b.get_tuning("group_overlap") == int(entries[key]["group_overlap"])
     got = [{k: _host(v) for k, v in o.items()} for o in b.submit()]
     for e, g in zip(ref, got):
         for k in e:
