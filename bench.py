@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 MI355X_HBM_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz: the FP32 vector
 # rate of plain v_fma_f32.  Packed FP32 (v_pk_fma_f32) would double it to the
-# published 157.3 TFLOP/s but is disabled in this build.
+# published 157.3 TFLOP/s; the library is compiled without packed FP32.
 MI355X_FP32_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 MI355X_FP32_PACKED_TFLOPS = 157.3
 # dense FP32 matrix-core rate: v_mfma_f32_16x16x4f32 is 16*16*4 FMAs per SIMD
@@ -768,7 +768,8 @@ def main():
         copy_calibration(args.copy_calibration_mib)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU (the multi-GPU split is a "
+                                   "design only); --gpus must be 1"}))
         sys.exit(2)
     if args.only == "fwd_bwd":
         print(json.dumps({"fwd_bwd": fwd_bwd(args)}), flush=True)
