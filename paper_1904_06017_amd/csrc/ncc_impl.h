@@ -87,37 +87,59 @@ struct NccGeom {
 constexpr int NC_TX4 = 60;
 // 4x4 transpose within each quad of lanes (lane c of a quad holds v[0..3];
 // afterwards v[k] holds what lane k held in element c): two butterfly stages
-// of DPP quad permutations, swapping the off-diagonal 2x2 blocks.
-__device__ __forceinline__ float dpp_quad_xor1(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float dpp_quad_xor2(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x4E, 0xF, 0xF, false));
-}
-__device__ __forceinline__ void quad_transpose4(float (&v)[4], int lane) {
-  const bool b0 = lane & 1, b1 = lane & 2;
+// that swap the off-diagonal 2x2 blocks.  Each element of a stage is one
+// v_cndmask_b32 whose first source is read through a DPP quad permutation:
+// lanes whose bit (0, then 1) equals that of k keep v[k], the others take
+// the partner lane's v[k ^ 1] (v[k ^ 2]).  The condition is a constant lane
+// pattern in VCC; s_nop 1 gives the two wait states a DPP read needs after
+// the VALU write of its source.  Every lane of a quad must be active.
+__device__ __forceinline__ void quad_transpose4(float (&v)[4]) {
   float t[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) t[k] = dpp_quad_xor1(v[k ^ 1]);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) v[k] = (b0 != (bool)(k & 1)) ? t[k] : v[k];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) t[k] = dpp_quad_xor2(v[k ^ 2]);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) v[k] = (b1 != (bool)(k & 2)) ? t[k] : v[k];
+  // lanes c and c ^ 1: (0, 1) and (2, 3); outputs 0, 2 keep where bit 0 is clear
+  asm volatile("s_nop 1\n\t"
+               "s_mov_b32 vcc_lo, 0x55555555\n\t"
+               "s_mov_b32 vcc_hi, 0x55555555\n\t"
+               "v_cndmask_b32_dpp %0, %5, %4, vcc quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+               "v_cndmask_b32_dpp %2, %7, %6, vcc quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+               "s_mov_b32 vcc_lo, 0xaaaaaaaa\n\t"
+               "s_mov_b32 vcc_hi, 0xaaaaaaaa\n\t"
+               "v_cndmask_b32_dpp %1, %4, %5, vcc quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+               "v_cndmask_b32_dpp %3, %6, %7, vcc quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf"
+               : "=&v"(t[0]), "=&v"(t[1]), "=&v"(t[2]), "=&v"(t[3])
+               : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3])
+               : "vcc");
+  // lanes c and c ^ 2: (0, 2) and (1, 3); outputs 0, 1 keep where bit 1 is clear
+  asm volatile("s_nop 1\n\t"
+               "s_mov_b32 vcc_lo, 0x33333333\n\t"
+               "s_mov_b32 vcc_hi, 0x33333333\n\t"
+               "v_cndmask_b32_dpp %0, %6, %4, vcc quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+               "v_cndmask_b32_dpp %1, %7, %5, vcc quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+               "s_mov_b32 vcc_lo, 0xcccccccc\n\t"
+               "s_mov_b32 vcc_hi, 0xcccccccc\n\t"
+               "v_cndmask_b32_dpp %2, %4, %6, vcc quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+               "v_cndmask_b32_dpp %3, %5, %7, vcc quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf"
+               : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3])
+               : "v"(t[0]), "v"(t[1]), "v"(t[2]), "v"(t[3])
+               : "vcc");
 }
 
-// v = hi + lo in FP16 (round to nearest; lo rounds the exact remainder),
-// four values packed two per register.
+// v = hi + lo in FP16 (round to nearest; lo rounds the remainder v - hi,
+// which is exact in FP32 and formed by one mixed-precision FMA reading hi
+// from its half of the packed register), four values packed two per register.
 __device__ __forceinline__ void split4_f16(const float (&v)[4], uint2& hi, uint2& lo) {
-  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-  typedef float f2 __attribute__((ext_vector_type(2)));
-  const h2 h01 = __builtin_convertvector((f2){v[0], v[1]}, h2);
-  const h2 h23 = __builtin_convertvector((f2){v[2], v[3]}, h2);
-  const h2 l01 = __builtin_convertvector((f2){v[0] - (float)h01.x, v[1] - (float)h01.y}, h2);
-  const h2 l23 = __builtin_convertvector((f2){v[2] - (float)h23.x, v[3] - (float)h23.y}, h2);
-  hi = make_uint2(__builtin_bit_cast(unsigned, h01), __builtin_bit_cast(unsigned, h23));
-  lo = make_uint2(__builtin_bit_cast(unsigned, l01), __builtin_bit_cast(unsigned, l23));
+  unsigned h[2], l[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    float r0, r1;
+    asm volatile("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(h[j]) : "v"(v[2 * j]), "v"(v[2 * j + 1]));
+    asm volatile("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]"
+                 : "=v"(r0) : "v"(h[j]), "v"(v[2 * j]));
+    asm volatile("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+                 : "=v"(r1) : "v"(h[j]), "v"(v[2 * j + 1]));
+    asm volatile("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(l[j]) : "v"(r0), "v"(r1));
+  }
+  hi = make_uint2(h[0], h[1]);
+  lo = make_uint2(l[0], l[1]);
 }
 
 // Copy N elements (two floats each) into LDS with NT threads: element i =
@@ -300,7 +322,7 @@ __device__ __forceinline__ void ncc_body_a(const T* __restrict__ ref, int64_t re
 #pragma unroll
               for (int k = 0; k < NC_DW; ++k) u[k] = (m >= 0 && m < W) ? u[k] : 0.0f;
             }
-            quad_transpose4(v, lane);
+            quad_transpose4(v);
             const int dl = db + (lane & 3);
             const bool full = QUAD != 4 || lane < NC_TX4;
             if (dl < ((d_end + 15) & ~15) && full) {
@@ -316,7 +338,7 @@ __device__ __forceinline__ void ncc_body_a(const T* __restrict__ ref, int64_t re
               }
             }
             if (QUAD == 4 && C2) {
-              quad_transpose4(u, lane);
+              quad_transpose4(u);
               // target-anchored stored column quad: x0 + pad = 60 bx and the
               // wave's first level are multiples of 4
               const int s1 = NC_TX4 * bx + 4 * (lane >> 2) - db;
