@@ -91,12 +91,14 @@ constexpr int NC_TX4 = 60;
 // v_cndmask_b32 whose first source is read through a DPP quad permutation:
 // lanes whose bit (0, then 1) equals that of k keep v[k], the others take
 // the partner lane's v[k ^ 1] (v[k ^ 2]).  The condition is a constant lane
-// pattern in VCC; s_nop 1 gives the two wait states a DPP read needs after
-// the VALU write of its source.  Every lane of a quad must be active.
+// pattern in VCC.  The compiler cannot see the DPP reads inside the asm, so
+// each stage opens with s_nop 4: the five wait states a DPP read needs after
+// a VALU write of EXEC, which also covers the two it needs after a VALU
+// write of its source.  Every lane of a quad must be active.
 __device__ __forceinline__ void quad_transpose4(float (&v)[4]) {
   float t[4];
   // lanes c and c ^ 1: (0, 1) and (2, 3); outputs 0, 2 keep where bit 0 is clear
-  asm volatile("s_nop 1\n\t"
+  asm volatile("s_nop 4\n\t"
                "s_mov_b32 vcc_lo, 0x55555555\n\t"
                "s_mov_b32 vcc_hi, 0x55555555\n\t"
                "v_cndmask_b32_dpp %0, %5, %4, vcc quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
@@ -109,7 +111,7 @@ __device__ __forceinline__ void quad_transpose4(float (&v)[4]) {
                : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3])
                : "vcc");
   // lanes c and c ^ 2: (0, 2) and (1, 3); outputs 0, 1 keep where bit 1 is clear
-  asm volatile("s_nop 1\n\t"
+  asm volatile("s_nop 4\n\t"
                "s_mov_b32 vcc_lo, 0x33333333\n\t"
                "s_mov_b32 vcc_hi, 0x33333333\n\t"
                "v_cndmask_b32_dpp %0, %6, %4, vcc quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
